@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Training-step benchmark of the Defrise-Clack FBP path on one MI355X.
+
+Workload (C2): sinusoidal orbit (source elevation amplitude 100 mm, 2 periods),
+496 views, SID 750 / SDD 1200 mm, 512 x 512 detector at 0.6 mm, Radon grid
+360 angles x 725 bins, 256^3 volume at 0.5 mm.  Data: 20 seeded random
+ellipsoids, exact line integrals, Poisson noise at 1e5 photons per ray; target =
+the voxelised phantom.  One step = forward (weighted Radon, filter, detector BP,
+cone BP + ReLU), MSE loss gradient, backward through every adjoint kernel to
+dL/dM, and an Adam update of M.  All inputs are resident in HBM before timing.
+
+Prints one JSON line: voxel-view updates per second (Nvox x V / step time) for
+float32 storage (``value``) and bf16 storage of H / gF (``bf16``), per-kernel
+times, the dominant kernel's roofline and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-view updates/s (fwd+bwd DC-FBP) at 256³; % HBM roofline; BF16 vs FP32"
+HBM_PEAK_GBS = 8000.0
+# float32 vector peak for non-packed FMA: 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6
+FP32_PEAK_PUBLISHED = 157.3
+
+# algorithmic work per unit (flops) of each stage, see the design doc
+FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 8, "cone_bp": 25,
+                  "cone_bp_adjoint": 25, "detector_bp_adjoint": 9, "filter_adjoint": 10}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def stage_work(g, V, bpe_store):
+    """(units, algorithmic HBM bytes) per launch over all V views."""
+    npix, nbin, nvox = g.nu * g.nv, g.n_theta * g.n_s, g.nx * g.ny * g.nz
+    pa = V * npix * g.n_theta            # pixel-angle pairs
+    vv = V * nvox                        # voxel-view pairs
+    return {
+        "weight_radon": (pa, V * npix * 4 + V * nbin * 4),
+        "filter": (V * nbin, V * nbin * (4 + 4 + bpe_store)),
+        "detector_bp": (pa, V * nbin * bpe_store + V * npix * bpe_store),
+        "cone_bp": (vv, V * npix * bpe_store + nvox * 4),
+        "cone_bp_adjoint": (vv, nvox * 4 * 2 + V * npix * 4),
+        "detector_bp_adjoint": (pa, V * npix * 4 + V * nbin * bpe_store),
+        "filter_adjoint": (V * nbin, V * nbin * (bpe_store + 4 + 4)),
+    }
+
+
+def cpu_baseline(grid, views, n_views=1):
+    """Times the float64 oracle on a bounded sample: n_views views of the same
+    step (forward + backward to dL/dM) at full detector, sinogram and volume size."""
+    import numpy as np
+    from oracle import pipeline as O
+    sub = views.subset(list(range(n_views)))
+    rng = np.random.Generator(np.random.PCG64(0))
+    g = rng.uniform(0, 1, (n_views, grid.nv, grid.nu))
+    M = np.full((n_views, grid.n_theta, grid.n_s), 0.5)
+    t0 = time.perf_counter()
+    R = O.weight_radon(g, grid, sub)
+    H = O.filter_stack(R, M, grid, sub)
+    gF = O.detector_bp(H, grid)
+    f = O.cone_bp(gF, grid, sub, relu=True)
+    GgF = O.cone_bp_adjoint(f, grid, sub, relu_f=f)
+    GH = O.detector_bp_adjoint(GgF, grid)
+    O.filter_stack_adjoint(GH, R, M, grid, sub)
+    dt = time.perf_counter() - t0
+    nvox = grid.nx * grid.ny * grid.nz
+    return {"value": nvox * n_views / dt, "unit": "voxel-view updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d views of the same forward+backward step (full 512^2 detector, 360x725 sinogram, "
+                      "256^3 volume), float64 NumPy, single thread; %.1f s" % (n_views, len(views), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", choices=["f32", "bf16", "both"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this path is single-GPU (views would shard across GPUs "
+              "with one all-reduce of the volume, which is not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2410_14900_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    cfg = synth.CONFIGS["C2"]
+    grid, views = synth.config_geometry("C2")
+    V = len(views)
+    nvox = grid.nx * grid.ny * grid.nz
+    log("geometry C2", grid.as_dict(), "views", V)
+
+    ell = synth.random_ellipsoids(cfg["n_ell"], grid.nx * grid.vx, cfg["seed"])
+    g64 = synth.project_ellipsoids(ell, grid, views, device="cuda")
+    g = synth.add_poisson_noise(g64, cfg["noise"], seed=cfg["seed"]).float().contiguous()
+    del g64
+    target = synth.voxelize_torch(ell, grid, device="cuda")
+    plan = P.Plan(grid, views)
+    torch.cuda.synchronize()
+    log("inputs ready")
+
+    results = {}
+    stream = torch.cuda.current_stream()
+    for store in (["f32", "bf16"] if args.dtype == "both" else [args.dtype]):
+        sdt = torch.float32 if store == "f32" else torch.bfloat16
+        bpe = 4 if store == "f32" else 2
+        K, S = grid.n_theta, grid.n_s
+        R = torch.empty((V, K, S), device="cuda")
+        H = torch.empty((V, K, S), device="cuda", dtype=sdt)
+        gF = torch.empty((V, grid.nv, grid.nu), device="cuda", dtype=sdt)
+        f = torch.empty((grid.nz, grid.ny, grid.nx), device="cuda")
+        GgF = torch.empty((V, grid.nv, grid.nu), device="cuda")
+        GH = torch.empty((V, K, S), device="cuda", dtype=sdt)
+        M = torch.full((V, K, S), 0.5, device="cuda", requires_grad=True)
+        GM = torch.empty((V, K, S), device="cuda")
+        opt = torch.optim.Adam([M], lr=1e-2)
+        stages = ["weight_radon", "filter", "detector_bp", "cone_bp", "cone_bp_adjoint",
+                  "detector_bp_adjoint", "filter_adjoint"]
+        ev = {s: [] for s in stages}
+        loss_box = {}
+
+        def run(record):
+            def timed(name, fn):
+                if record:
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    fn()
+                    b.record(stream)
+                    ev[name].append((a, b))
+                else:
+                    fn()
+            Md = M.detach()
+            timed("weight_radon", lambda: P.dc_weight_radon(plan, g, R))
+            timed("filter", lambda: P.dc_filter(plan, R, Md, H))
+            timed("detector_bp", lambda: P.dc_detector_bp(plan, H, gF))
+            timed("cone_bp", lambda: P.dc_cone_bp(plan, gF, f, relu=True))
+            diff = f - target
+            loss_box["loss"] = (diff * diff).mean()
+            Gf = diff * (2.0 / nvox)
+            timed("cone_bp_adjoint", lambda: P.dc_cone_bp_adjoint(plan, Gf, GgF, f_relu=f))
+            timed("detector_bp_adjoint", lambda: P.dc_detector_bp_adjoint(plan, GgF, GH))
+            timed("filter_adjoint", lambda: P.dc_filter_adjoint(plan, GH, R, Md, GM=GM))
+            M.grad = GM
+            opt.step()
+
+        for _ in range(args.warmup):
+            run(False)
+        torch.cuda.synchronize()
+        log(store, "warmup done, loss", float(loss_box["loss"]))
+        t0 = time.perf_counter()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            run(True)
+        end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(end) / args.steps
+        kern = {s: sum(a.elapsed_time(b) for a, b in ev[s]) / len(ev[s]) for s in stages}
+        log(store, "ms/step %.2f (wall %.2f)" % (ms, 1e3 * wall / args.steps), json.dumps(kern))
+        work = stage_work(grid, V, bpe)
+        per_kernel = {}
+        for s in stages:
+            units, byts = work[s]
+            t = kern[s] * 1e-3
+            per_kernel[s] = {"ms": round(kern[s], 3), "GB/s": round(byts / t / 1e9, 1),
+                             "TFLOP/s": round(units * FLOPS_PER_UNIT[s] / t / 1e12, 2)}
+        results[store] = dict(ms=ms, kern=kern, per_kernel=per_kernel, work=work,
+                              loss=float(loss_box["loss"]))
+        del R, H, gF, f, GgF, GH, M, GM, opt
+        torch.cuda.empty_cache()
+
+    main_store = "f32" if "f32" in results else "bf16"
+    r = results[main_store]
+    dom = max(r["kern"], key=r["kern"].get)
+    units, byts = r["work"][dom]
+    t = r["kern"][dom] * 1e-3
+    if dom.startswith("filter"):
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(byts / t / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        ach = units * FLOPS_PER_UNIT[dom] / t / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
+                "peak_published_packed": FP32_PEAK_PUBLISHED, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "hbm_GBps": round(byts / t / 1e9, 1)}
+    out = {
+        "metric": METRIC,
+        "value": nvox * V / (r["ms"] * 1e-3),
+        "unit": "voxel-view updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if main_store == "f32" else "bf16-storage/f32-accumulate",
+        "data": "synthetic: 20 seeded random ellipsoids, exact line integrals, Poisson noise at 1e5 photons/ray",
+        "config": {"workload": "C2: sinusoidal orbit, 496 views, 512x512 detector @0.6 mm, Radon 360x725, "
+                               "256^3 volume @0.5 mm, forward+backward w.r.t. M + Adam step",
+                   "views": V, "detector": [grid.nv, grid.nu], "radon": [grid.n_theta, grid.n_s],
+                   "volume": [grid.nz, grid.ny, grid.nx]},
+        "roofline": roof,
+        "kernels": r["per_kernel"],
+    }
+    if "bf16" in results and main_store == "f32":
+        b = results["bf16"]
+        out["bf16"] = {"value": nvox * V / (b["ms"] * 1e-3), "ms_per_step": round(b["ms"], 3),
+                       "kernels": b["per_kernel"], "speedup_vs_f32": round(r["ms"] / b["ms"], 3)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(grid, views, args.cpu_views)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,145 @@
+/*
+ * dcfbp.h -- C ABI of the MI355X (gfx950) Defrise-Clack shift-variant FBP library.
+ *
+ * The library computes, per cone-beam view lambda, the chain of the paper's
+ * eq. 12 (Ye et al., "DRACO: Differentiable Reconstruction for Arbitrary CBCT
+ * Orbits", Sec. 2.3-2.4):
+ *
+ *     f = A3d^T w_d A2d^T D w_red w_sino D A2d w_cos g
+ *
+ * split into four stages, each with its exact transpose:
+ *
+ *   dc_weight_radon   g  -> R  = A2d(w_cos g)                 (eq. 7, before D)
+ *   dc_filter         R  -> H  = D( M c_geo (D R) )            (eqs. 7, 10, 11)
+ *   dc_detector_bp    H  -> gF = A2d^T H                       (eq. 8 / 11, w_d folded)
+ *   dc_cone_bp        gF -> f  = sum_v (D/U)^2 bilinear(gF_v)  (eq. 5 with w_d, ReLU)
+ *
+ * Discretisation (identical to the float64 reference it is tested against):
+ *   detector pixel (i,j) at x_i = (i-(nu-1)/2) du, y_j = (j-(nv-1)/2) dv in the
+ *   detector frame (origin at the detector centre, l_z = l_x x l_y towards the
+ *   source, Fig. 1); Radon angles mu_k = k pi/n_theta (range pi, Table 2),
+ *   bins s_m = (m-(n_s-1)/2) ds; A2d^T = pixel-driven linear interpolation of each
+ *   sinogram row summed over mu with weight pi/n_theta; A2d = its transpose times
+ *   du dv/ds; D = zero-padded central difference along s;
+ *   c_geo = -|D t.n_mu + s t.l_z| / (4 pi^2 D^2) with t = a'(lambda) dlambda, the
+ *   collapse of w_sino * w_red (eqs. 7, 10) for theta = (D n_mu + s l_z)/sqrt(s^2+D^2);
+ *   the detector weight w_d = x^2+y^2+D^2 (eq. 11) and eq. 5's 1/|x-a|^2 combine at
+ *   each voxel's exact projection into D^2/U^2, U = (a-x).l_z; bilinear
+ *   interpolation with zero outside the detector.
+ *
+ * Layouts (contiguous, row-major, last index fastest):
+ *   g, gF, Gg, GgF : [V][nv][nu]     R, H, M, GM, GR, GH : [V][n_theta][n_s]
+ *   f, Gf          : [nz][ny][nx]
+ * Every stage call takes pointers to the FULL per-view arrays and processes the
+ * view range [v0, v0+nv); volumes are shared by all views.
+ *
+ * Calling convention for every stage call: device pointers, enqueued on `stream`,
+ * asynchronous, no allocation, no host synchronisation; base pointers 16-byte
+ * aligned.  Errors are returned as dc_status before anything is enqueued (shape,
+ * dtype, alignment, view range); dc_last_error() gives a thread-local message.
+ * A fault inside a kernel surfaces at the caller's next synchronisation.
+ * Ownership: the caller owns every array; the plan owns only its small device
+ * tables, is immutable after creation and must be created before any stream
+ * capture that uses it.
+ */
+#ifndef DCFBP_H
+#define DCFBP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DC_OK = 0, DC_EINVAL = 1, DC_ESHAPE = 2, DC_EDTYPE = 3, DC_EALIGN = 4,
+  DC_EHIP = 5, DC_ENOTSUP = 6, DC_ENOMEM = 7
+} dc_status;
+
+/* storage type of R, H, gF and their gradients; arithmetic is always float32 */
+typedef enum { DC_F32 = 0, DC_BF16 = 1, DC_F16 = 2 } dc_dtype;
+
+/* ANALYTIC: W = M * c_geo (M replaces 1/n, eq. 8/9);  RAW: W = M (the whole
+ * redundancy weight of eq. 10 is the learned parameter, as the paper trains it) */
+typedef enum { DC_WEIGHT_ANALYTIC = 0, DC_WEIGHT_RAW = 1 } dc_wmode;
+
+typedef struct {
+  int32_t nu, nv;          /* detector columns (along l_x) and rows (along l_y) */
+  double  du, dv;          /* pixel pitch, mm */
+  int32_t n_theta, n_s;    /* Radon grid: angles over [0, pi) and s bins */
+  double  ds;              /* s bin width, mm */
+  int32_t nx, ny, nz;      /* volume size */
+  double  vx, vy, vz;      /* voxel size, mm */
+  double  ox, oy, oz;      /* volume centre in world coordinates, mm */
+} dc_grid;
+
+/* One view (Fig. 1): source a, detector centre O, in-plane unit vectors l_x, l_y
+ * (l_z = l_x x l_y points to the source; the source must lie on the detector
+ * normal through O), and the orbit tangent already scaled by the view spacing,
+ * t = a'(lambda) dlambda (mm).  All in world mm. */
+typedef struct {
+  double src[3], det_center[3], ex[3], ey[3], tangent[3];
+} dc_view;
+
+typedef struct dc_plan_s* dc_plan;
+
+/* Host-only geometry check (no GPU needed): positive sizes and pitches,
+ * orthonormal detector axes, source on the detector normal through its centre
+ * (relative 1e-6), every voxel-box corner strictly in front of the source
+ * (U > 0).  Returns DC_OK, DC_EINVAL or DC_ESHAPE. */
+dc_status dc_validate(const dc_grid* grid, const dc_view* views, int32_t n_views);
+
+/* Builds a plan on the current HIP device: copies grid and views, derives the
+ * per-view projection tables in float64 and uploads them (small allocations made
+ * here, never in a stage call).  flags must be 0.  *out is set only on DC_OK. */
+dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_views,
+                         uint32_t flags, dc_plan* out);
+dc_status dc_plan_destroy(dc_plan plan);
+/* Thread-local text of the last error (empty string if none). */
+const char* dc_last_error(void);
+/* Size queries used by bindings: views, and the grid the plan was built with. */
+int32_t dc_plan_n_views(dc_plan plan);
+dc_status dc_plan_grid(dc_plan plan, dc_grid* out);
+
+/* Stage 1, eq. 7 (integrate first): R[v] = (du dv/ds) sum_p w_cos(p) g[v](p) Lambda((s_p,k - s_m)/ds),
+ * w_cos = D/sqrt(x^2+y^2+D^2).  g float32; R stored as tR. */
+dc_status dc_weight_radon(dc_plan plan, const float* g, void* R, dc_dtype tR,
+                          int32_t v0, int32_t nv, hipStream_t stream);
+/* Exact transpose of dc_weight_radon: Gg[v] = w_cos (du dv/ds) interp(GR[v]).  Gg float32, overwritten. */
+dc_status dc_weight_radon_adjoint(dc_plan plan, const void* GR, dc_dtype tR, float* Gg,
+                                  int32_t v0, int32_t nv, hipStream_t stream);
+
+/* Stage 2, eqs. 7, 10, 11: Q = D R, P = W Q, H = D P, W per mode (see dc_wmode). M float32. */
+dc_status dc_filter(dc_plan plan, const void* R, dc_dtype tR, const float* M, dc_wmode mode,
+                    void* H, dc_dtype tH, int32_t v0, int32_t nv, hipStream_t stream);
+/* Transpose of dc_filter w.r.t. R and gradient w.r.t. M given GH = dL/dH:
+ *   GP = D^T GH (= -D GH),  GM (+)= GP * (D R) * c_geo   (c_geo = 1 in RAW mode),
+ *   GR = D^T (W * GP).
+ * GM (float32) and GR (float32) may each be NULL to skip; accumulate_GM != 0 adds into GM. */
+dc_status dc_filter_adjoint(dc_plan plan, const void* GH, dc_dtype tH, const void* R, dc_dtype tR,
+                            const float* M, dc_wmode mode, float* GM, int32_t accumulate_GM,
+                            float* GR, int32_t v0, int32_t nv, hipStream_t stream);
+
+/* Stage 3, eq. 8 / 11: gF[v](i,j) = (pi/n_theta) sum_k lerp(H[v][k], s = x_i cos mu_k + y_j sin mu_k). */
+dc_status dc_detector_bp(dc_plan plan, const void* H, dc_dtype tH, void* gF, dc_dtype tF,
+                         int32_t v0, int32_t nv, hipStream_t stream);
+/* Exact transpose of dc_detector_bp (the detector Radon): GH[v] = (pi/n_theta) splat(GgF[v]). */
+dc_status dc_detector_bp_adjoint(dc_plan plan, const void* GgF, dc_dtype tF, void* GH, dc_dtype tH,
+                                 int32_t v0, int32_t nv, hipStream_t stream);
+
+/* Stage 4, eq. 5 with w_d folded: f(x) (+)= sum_{v in range} (D/U)^2 bilinear(gF[v], proj_v(x)).
+ * accumulate != 0 adds to f; relu != 0 applies max(., 0) to the result (set it
+ * only on the call that completes the view sum, paper Sec. 2.4). */
+dc_status dc_cone_bp(dc_plan plan, const void* gF, dc_dtype tF, float* f, int32_t accumulate,
+                     int32_t relu, int32_t v0, int32_t nv, hipStream_t stream);
+/* Exact transpose of dc_cone_bp (cone-beam forward projection of Gf):
+ * GgF[v](p) = sum_x (D/U)^2 Gf'(x) bilinear-weight(x -> p), Gf' = Gf * [f_relu > 0]
+ * when f_relu (the ReLU output of the forward) is non-NULL, else Gf.  GgF overwritten. */
+dc_status dc_cone_bp_adjoint(dc_plan plan, const float* Gf, const float* f_relu, void* GgF,
+                             dc_dtype tF, int32_t v0, int32_t nv, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCFBP_H */

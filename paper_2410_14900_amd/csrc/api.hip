@@ -1,0 +1,355 @@
+// Host side of the C ABI: validation, plan construction in float64, argument
+// checking and dispatch to the kernel launchers.  Nothing here allocates or
+// synchronises inside a stage call.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dc_internal.h"
+
+namespace dc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static dc_status fail(dc_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+static inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static dc_status validate(const dc_grid* g, const dc_view* views, int32_t n) {
+  if (!g || !views) return fail(DC_EINVAL, "null grid or views");
+  if (n < 1) return fail(DC_ESHAPE, "n_views must be >= 1");
+  if (g->nu < 1 || g->nv < 1 || g->n_theta < 1 || g->n_s < 2 || g->nx < 1 || g->ny < 1 || g->nz < 1)
+    return fail(DC_ESHAPE, "grid sizes must be positive (n_s >= 2)");
+  const double lim = 2147483647.0;
+  if ((double)g->nu * g->nv > lim / 4 || (double)g->n_theta * g->n_s > lim / 4 ||
+      (double)g->nx * g->ny * g->nz > lim / 4)
+    return fail(DC_ESHAPE, "per-view image, sinogram or volume too large for 32-bit indexing");
+  if (g->n_s > 4096) return fail(DC_ESHAPE, "n_s above 4096 not supported (sinogram rows are staged in LDS)");
+  if (!(g->du > 0 && g->dv > 0 && g->ds > 0 && g->vx > 0 && g->vy > 0 && g->vz > 0))
+    return fail(DC_EINVAL, "pitches and voxel sizes must be positive");
+  const double hx = 0.5 * g->nx * g->vx, hy = 0.5 * g->ny * g->vy, hz = 0.5 * g->nz * g->vz;
+  for (int v = 0; v < n; ++v) {
+    const dc_view& w = views[v];
+    double nx_ = std::sqrt(dot3(w.ex, w.ex)), ny_ = std::sqrt(dot3(w.ey, w.ey));
+    if (std::fabs(nx_ - 1) > 1e-9 || std::fabs(ny_ - 1) > 1e-9 || std::fabs(dot3(w.ex, w.ey)) > 1e-9)
+      return fail(DC_EINVAL, "view " + std::to_string(v) + ": detector axes not orthonormal");
+    double lz[3], d[3];
+    cross3(w.ex, w.ey, lz);
+    for (int c = 0; c < 3; ++c) d[c] = w.src[c] - w.det_center[c];
+    double D = dot3(d, lz);
+    if (!(D > 0)) return fail(DC_EINVAL, "view " + std::to_string(v) + ": source not in front of the detector");
+    double off = 0;
+    for (int c = 0; c < 3; ++c) off += (d[c] - D * lz[c]) * (d[c] - D * lz[c]);
+    if (std::sqrt(off) > 1e-6 * D)
+      return fail(DC_EINVAL, "view " + std::to_string(v) + ": source not on the detector normal through its centre");
+    for (int corner = 0; corner < 8; ++corner) {
+      double p[3] = {g->ox + ((corner & 1) ? hx : -hx), g->oy + ((corner & 2) ? hy : -hy),
+                     g->oz + ((corner & 4) ? hz : -hz)};
+      double U = 0;
+      for (int c = 0; c < 3; ++c) U += (w.src[c] - p[c]) * lz[c];
+      if (!(U > 1e-6 * D))
+        return fail(DC_EINVAL, "view " + std::to_string(v) + ": volume not entirely in front of the source");
+    }
+  }
+  return DC_OK;
+}
+
+static const int kInterpTX = 32, kInterpTY = 16;
+
+static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, Plan* p) {
+  p->grid = *g;
+  p->n_views = n;
+  KGrid& k = p->kg;
+  k.nu = g->nu; k.nv = g->nv; k.n_theta = g->n_theta; k.n_s = g->n_s;
+  k.nx = g->nx; k.ny = g->ny; k.nz = g->nz;
+  k.du = (float)g->du; k.dv = (float)g->dv; k.ds = (float)g->ds;
+  k.cu = 0.5f * (g->nu - 1); k.cv = 0.5f * (g->nv - 1);
+
+  const int K = g->n_theta;
+  std::vector<double> ang(3 * K);
+  std::vector<float> angf(4 * K), trig(2 * K);
+  const double x0 = -0.5 * (g->nu - 1) * g->du, y0 = -0.5 * (g->nv - 1) * g->dv;
+  int wl = 0;
+  for (int kk = 0; kk < K; ++kk) {
+    double mu = kk * M_PI / K, c = std::cos(mu), s = std::sin(mu);
+    double A = g->du * c / g->ds, B = g->dv * s / g->ds;
+    double C = (x0 * c + y0 * s) / g->ds + 0.5 * (g->n_s - 1);
+    ang[3 * kk] = A; ang[3 * kk + 1] = B; ang[3 * kk + 2] = C;
+    angf[4 * kk] = (float)A; angf[4 * kk + 1] = (float)B; angf[4 * kk + 2] = (float)C; angf[4 * kk + 3] = 0.f;
+    trig[2 * kk] = (float)c; trig[2 * kk + 1] = (float)s;
+    int w = (int)std::ceil((kInterpTX - 1) * std::fabs(A) + (kInterpTY - 1) * std::fabs(B)) + 4;
+    if (w > wl) wl = w;
+  }
+  p->interp_wl = wl;
+  if (wl > 256) return fail(DC_ENOTSUP, "detector pitch too coarse for the s-bin width (ds << du)");
+
+  // Radon work list: runs of angles whose pixels spread fastest along rows
+  // (|A| >= |B|, lanes walk i) or along columns (lanes walk j), cut into chunks.
+  const int kc = std::max(1, std::min(16, 16384 / g->n_s));
+  p->splat_kc = kc;
+  std::vector<int> chunks;
+  for (int kk = 0; kk < K;) {
+    int colmajor = std::fabs(ang[3 * kk + 1]) > std::fabs(ang[3 * kk]) ? 1 : 0;
+    int e = kk;
+    while (e < K && e - kk < kc &&
+           (std::fabs(ang[3 * e + 1]) > std::fabs(ang[3 * e]) ? 1 : 0) == colmajor) ++e;
+    chunks.insert(chunks.end(), {kk, e - kk, colmajor, 0});
+    kk = e;
+  }
+  p->n_chunks = (int)chunks.size() / 4;
+
+  std::vector<float> vf(4 * n);
+  std::vector<double> proj(12 * n);
+  const double X0[3] = {-0.5 * (g->nx - 1) * g->vx + g->ox, -0.5 * (g->ny - 1) * g->vy + g->oy,
+                        -0.5 * (g->nz - 1) * g->vz + g->oz};
+  const double vs[3] = {g->vx, g->vy, g->vz};
+  const double four_pi2 = 4.0 * M_PI * M_PI;
+  for (int v = 0; v < n; ++v) {
+    const dc_view& w = views[v];
+    double lz[3], d[3];
+    cross3(w.ex, w.ey, lz);
+    for (int c = 0; c < 3; ++c) d[c] = w.src[c] - w.det_center[c];
+    double D = dot3(d, lz);
+    vf[4 * v] = (float)D;
+    vf[4 * v + 1] = (float)(dot3(w.tangent, w.ex) / (four_pi2 * D));
+    vf[4 * v + 2] = (float)(dot3(w.tangent, w.ey) / (four_pi2 * D));
+    vf[4 * v + 3] = (float)(dot3(w.tangent, lz) / (four_pi2 * D * D));
+    double rel0[3];
+    for (int c = 0; c < 3; ++c) rel0[c] = X0[c] - w.src[c];
+    double* P = &proj[12 * v];
+    for (int c = 0; c < 3; ++c) {
+      double dn = -vs[c] * lz[c] / D;
+      P[c] = dn;
+      P[4 + c] = vs[c] * w.ex[c] / g->du + 0.5 * (g->nu - 1) * dn;
+      P[8 + c] = vs[c] * w.ey[c] / g->dv + 0.5 * (g->nv - 1) * dn;
+    }
+    double dn0 = -dot3(rel0, lz) / D;
+    P[3] = dn0;
+    P[7] = dot3(rel0, w.ex) / g->du + 0.5 * (g->nu - 1) * dn0;
+    P[11] = dot3(rel0, w.ey) / g->dv + 0.5 * (g->nv - 1) * dn0;
+  }
+
+  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e;
+  if ((e = up((void**)&p->d_ang, ang.data(), ang.size() * sizeof(double))) != hipSuccess ||
+      (e = up((void**)&p->d_angf, angf.data(), angf.size() * sizeof(float))) != hipSuccess ||
+      (e = up((void**)&p->d_trig, trig.data(), trig.size() * sizeof(float))) != hipSuccess ||
+      (e = up((void**)&p->d_view, vf.data(), vf.size() * sizeof(float))) != hipSuccess ||
+      (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
+      (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP,
+                std::string("plan upload: ") + hipGetErrorString(e));
+  return DC_OK;
+}
+
+static void free_plan(Plan* p) {
+  void* ptrs[] = {p->d_ang, p->d_angf, p->d_trig, p->d_view, p->d_proj, p->d_chunks};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+// ---------------------------------------------------------- call checking
+static dc_status check_call(const dc_plan plan, int32_t v0, int32_t nv) {
+  if (!plan) return fail(DC_EINVAL, "null plan");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (v0 < 0 || nv < 0 || (int64_t)v0 + nv > p->n_views)
+    return fail(DC_ESHAPE, "view range [" + std::to_string(v0) + ", " + std::to_string((int64_t)v0 + nv) +
+                               ") outside [0, " + std::to_string(p->n_views) + ")");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(DC_EINVAL, "current HIP device differs from the plan's device");
+  return DC_OK;
+}
+
+static dc_status check_ptr(const void* q, const char* name, bool nullable = false) {
+  if (!q) return nullable ? DC_OK : fail(DC_EINVAL, std::string("null pointer: ") + name);
+  if (reinterpret_cast<uintptr_t>(q) % 16 != 0)
+    return fail(DC_EALIGN, std::string("pointer not 16-byte aligned: ") + name);
+  return DC_OK;
+}
+
+static dc_status check_dtype(dc_dtype t, const char* name) {
+  if (t != DC_F32 && t != DC_BF16 && t != DC_F16) return fail(DC_EDTYPE, std::string("bad dtype for ") + name);
+  return DC_OK;
+}
+
+static dc_status launched(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(DC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return DC_OK;
+}
+
+#define DC_TRY(x)                  \
+  do {                             \
+    dc_status _st = (x);           \
+    if (_st != DC_OK) return _st;  \
+  } while (0)
+
+}  // namespace dc
+
+using namespace dc;
+
+extern "C" {
+
+const char* dc_last_error(void) { return g_last_error.c_str(); }
+
+dc_status dc_validate(const dc_grid* grid, const dc_view* views, int32_t n_views) {
+  return validate(grid, views, n_views);
+}
+
+dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_views, uint32_t flags,
+                         dc_plan* out) {
+  if (!out) return fail(DC_EINVAL, "null output plan pointer");
+  if (flags != 0) return fail(DC_EINVAL, "flags must be 0");
+  DC_TRY(validate(grid, views, n_views));
+  Plan* p = new Plan();
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(DC_EHIP, "no HIP device");
+  }
+  dc_status st = build_plan(grid, views, n_views, p);
+  if (st != DC_OK) {
+    free_plan(p);
+    return st;
+  }
+  *out = reinterpret_cast<dc_plan>(p);
+  return DC_OK;
+}
+
+dc_status dc_plan_destroy(dc_plan plan) {
+  if (!plan) return fail(DC_EINVAL, "null plan");
+  free_plan(reinterpret_cast<Plan*>(plan));
+  return DC_OK;
+}
+
+int32_t dc_plan_n_views(dc_plan plan) { return plan ? reinterpret_cast<Plan*>(plan)->n_views : -1; }
+
+dc_status dc_plan_grid(dc_plan plan, dc_grid* out) {
+  if (!plan || !out) return fail(DC_EINVAL, "null argument");
+  *out = reinterpret_cast<Plan*>(plan)->grid;
+  return DC_OK;
+}
+
+dc_status dc_weight_radon(dc_plan plan, const float* g, void* R, dc_dtype tR, int32_t v0, int32_t nv,
+                          hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(g, "g"));
+  DC_TRY(check_ptr(R, "R"));
+  DC_TRY(check_dtype(tR, "R"));
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  float scale = (float)(p.grid.du * p.grid.dv / p.grid.ds);
+  return launched(launch_splat(p, g, DC_F32, true, scale, R, tR, v0, nv, stream), "dc_weight_radon");
+}
+
+dc_status dc_weight_radon_adjoint(dc_plan plan, const void* GR, dc_dtype tR, float* Gg, int32_t v0,
+                                  int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(GR, "GR"));
+  DC_TRY(check_ptr(Gg, "Gg"));
+  DC_TRY(check_dtype(tR, "GR"));
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  float scale = (float)(p.grid.du * p.grid.dv / p.grid.ds);
+  return launched(launch_interp(p, GR, tR, true, scale, Gg, DC_F32, v0, nv, stream), "dc_weight_radon_adjoint");
+}
+
+dc_status dc_filter(dc_plan plan, const void* R, dc_dtype tR, const float* M, dc_wmode mode, void* H,
+                    dc_dtype tH, int32_t v0, int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(R, "R"));
+  DC_TRY(check_ptr(M, "M"));
+  DC_TRY(check_ptr(H, "H"));
+  DC_TRY(check_dtype(tR, "R"));
+  DC_TRY(check_dtype(tH, "H"));
+  if (mode != DC_WEIGHT_ANALYTIC && mode != DC_WEIGHT_RAW) return fail(DC_EINVAL, "bad weight mode");
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  return launched(launch_filter(p, R, tR, M, mode == DC_WEIGHT_RAW, H, tH, v0, nv, stream), "dc_filter");
+}
+
+dc_status dc_filter_adjoint(dc_plan plan, const void* GH, dc_dtype tH, const void* R, dc_dtype tR,
+                            const float* M, dc_wmode mode, float* GM, int32_t accumulate_GM, float* GR,
+                            int32_t v0, int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(GH, "GH"));
+  DC_TRY(check_ptr(R, "R"));
+  DC_TRY(check_ptr(M, "M"));
+  DC_TRY(check_ptr(GM, "GM", true));
+  DC_TRY(check_ptr(GR, "GR", true));
+  DC_TRY(check_dtype(tH, "GH"));
+  DC_TRY(check_dtype(tR, "R"));
+  if (mode != DC_WEIGHT_ANALYTIC && mode != DC_WEIGHT_RAW) return fail(DC_EINVAL, "bad weight mode");
+  if (nv == 0 || (!GM && !GR)) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  return launched(launch_filter_adjoint(p, GH, tH, R, tR, M, mode == DC_WEIGHT_RAW, GM, accumulate_GM, GR,
+                                        v0, nv, stream),
+                  "dc_filter_adjoint");
+}
+
+dc_status dc_detector_bp(dc_plan plan, const void* H, dc_dtype tH, void* gF, dc_dtype tF, int32_t v0,
+                         int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(H, "H"));
+  DC_TRY(check_ptr(gF, "gF"));
+  DC_TRY(check_dtype(tH, "H"));
+  DC_TRY(check_dtype(tF, "gF"));
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  float scale = (float)(M_PI / p.grid.n_theta);
+  return launched(launch_interp(p, H, tH, false, scale, gF, tF, v0, nv, stream), "dc_detector_bp");
+}
+
+dc_status dc_detector_bp_adjoint(dc_plan plan, const void* GgF, dc_dtype tF, void* GH, dc_dtype tH,
+                                 int32_t v0, int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(GgF, "GgF"));
+  DC_TRY(check_ptr(GH, "GH"));
+  DC_TRY(check_dtype(tF, "GgF"));
+  DC_TRY(check_dtype(tH, "GH"));
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  float scale = (float)(M_PI / p.grid.n_theta);
+  return launched(launch_splat(p, GgF, tF, false, scale, GH, tH, v0, nv, stream), "dc_detector_bp_adjoint");
+}
+
+dc_status dc_cone_bp(dc_plan plan, const void* gF, dc_dtype tF, float* f, int32_t accumulate, int32_t relu,
+                     int32_t v0, int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(gF, "gF"));
+  DC_TRY(check_ptr(f, "f"));
+  DC_TRY(check_dtype(tF, "gF"));
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  return launched(launch_cone_bp(p, gF, tF, f, accumulate, relu, v0, nv, stream), "dc_cone_bp");
+}
+
+dc_status dc_cone_bp_adjoint(dc_plan plan, const float* Gf, const float* f_relu, void* GgF, dc_dtype tF,
+                             int32_t v0, int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(Gf, "Gf"));
+  DC_TRY(check_ptr(f_relu, "f_relu", true));
+  DC_TRY(check_ptr(GgF, "GgF"));
+  DC_TRY(check_dtype(tF, "GgF"));
+  if (tF != DC_F32) return fail(DC_ENOTSUP, "dc_cone_bp_adjoint: GgF must be float32");
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  return launched(launch_cone_fp(p, Gf, f_relu, GgF, tF, v0, nv, stream), "dc_cone_bp_adjoint");
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/dcfbp.h"
+
+namespace dc {
+
+// ----------------------------------------------------------------- storage
+// Conversions between float32 arithmetic and the storage types of dc_dtype.
+struct bf16_t { uint16_t bits; };
+
+__device__ __forceinline__ float to_f32(float x) { return x; }
+__device__ __forceinline__ float to_f32(bf16_t x) { return __uint_as_float(uint32_t(x.bits) << 16); }
+__device__ __forceinline__ float to_f32(_Float16 x) { return float(x); }
+
+template <typename T> __device__ __forceinline__ T from_f32(float x);
+template <> __device__ __forceinline__ float from_f32<float>(float x) { return x; }
+template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float x) { return _Float16(x); }
+template <> __device__ __forceinline__ bf16_t from_f32<bf16_t>(float x) {
+  // round to nearest even; NaN stays NaN (quiet bit forced)
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return bf16_t{uint16_t((u >> 16) | 0x40u)};
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16_t{uint16_t(u >> 16)};
+}
+
+// Calls f with a value of the storage type selected at run time.
+template <typename F>
+static inline hipError_t by_dtype(dc_dtype t, F&& f) {
+  switch (t) {
+    case DC_F32: return f(float{});
+    case DC_BF16: return f(bf16_t{});
+    default: return f(_Float16{});
+  }
+}
+
+// ------------------------------------------------------------ kernel args
+// Scalar description of the sampling grids passed by value to every kernel.
+struct KGrid {
+  int nu, nv, n_theta, n_s, nx, ny, nz;
+  float du, dv, ds;
+  float cu, cv;          // (nu-1)/2, (nv-1)/2
+};
+
+// Plan: host copy of the geometry plus small device tables.
+struct Plan {
+  int device = 0;
+  dc_grid grid{};
+  int n_views = 0;
+  KGrid kg{};
+  // per angle k (float64): A_k = du cos mu/ds, B_k = dv sin mu/ds,
+  // C_k = fractional bin index of pixel (0,0)      -> t = i A + j B + C
+  double* d_ang = nullptr;       // [n_theta][3]
+  float* d_angf = nullptr;       // [n_theta][4]  (A, B, C, 0) rounded once
+  float* d_trig = nullptr;       // [n_theta][2]  cos mu, sin mu
+  // per view (float32): D, t.l_x/(4 pi^2 D), t.l_y/(4 pi^2 D), t.l_z/(4 pi^2 D^2)
+  float* d_view = nullptr;       // [V][4]
+  // per view (float64) projective map of voxel indices: rows den, num_u, num_v,
+  // each with coefficients of (ix, iy, iz, 1); i* = num_u/den, j* = num_v/den,
+  // den = U/D, weight (D/U)^2 = 1/den^2
+  double* d_proj = nullptr;      // [V][12]
+  // splat (Radon) work list: angle chunks that stay on one side of the diagonal
+  int4* d_chunks = nullptr;      // (k0, count, column_major, 0)
+  int n_chunks = 0;
+  int splat_kc = 0;              // max angles per chunk
+  int interp_wl = 0;             // LDS window length for the interpolating kernels
+};
+
+void set_error(const std::string& msg);
+
+// launchers (return hipSuccess or the launch error)
+hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale,
+                        void* out, dc_dtype t_out, int v0, int nv, hipStream_t s);
+hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wcos, float scale,
+                         void* out, dc_dtype t_out, int v0, int nv, hipStream_t s);
+hipError_t launch_filter(const Plan& p, const void* R, dc_dtype tR, const float* M, int raw,
+                         void* H, dc_dtype tH, int v0, int nv, hipStream_t s);
+hipError_t launch_filter_adjoint(const Plan& p, const void* GH, dc_dtype tH, const void* R,
+                                 dc_dtype tR, const float* M, int raw, float* GM, int acc,
+                                 float* GR, int v0, int nv, hipStream_t s);
+hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu,
+                          int v0, int nv, hipStream_t s);
+hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, void* GgF,
+                          dc_dtype tF, int v0, int nv, hipStream_t s);
+
+}  // namespace dc

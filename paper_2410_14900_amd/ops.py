@@ -1,0 +1,187 @@
+"""Torch-facing binding of the C ABI: same names as include/dcfbp.h.
+
+Only argument marshalling happens here: shapes and dtypes are checked, torch
+tensors are turned into device pointers, and the call is enqueued on torch's
+current stream.  Every arithmetic step runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DcGrid, DcView, check
+
+_DT = {torch.float32: _lib.DC_F32, torch.bfloat16: _lib.DC_BF16, torch.float16: _lib.DC_F16}
+MODES = {"analytic": _lib.DC_WEIGHT_ANALYTIC, "raw": _lib.DC_WEIGHT_RAW}
+
+
+def make_grid(grid) -> DcGrid:
+    d = grid if isinstance(grid, dict) else grid.__dict__
+    return DcGrid(**{k: d[k] for k, _ in DcGrid._fields_})
+
+
+def make_views(views):
+    arr = views.packed() if hasattr(views, "packed") else np.asarray(views, np.float64)
+    arr = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1, 15)
+    buf = (DcView * arr.shape[0])()
+    ctypes.memmove(buf, arr.ctypes.data, arr.nbytes)
+    return buf, arr.shape[0]
+
+
+def validate(grid, views):
+    """Host-only geometry check; returns (status, message)."""
+    g = make_grid(grid)
+    buf, n = make_views(views)
+    st = _lib.lib().dc_validate(ctypes.byref(g), buf, n)
+    return st, (_lib.last_error() if st else "")
+
+
+class Plan:
+    """Geometry plan on the current device (small float64-derived tables)."""
+
+    def __init__(self, grid, views):
+        self.grid = make_grid(grid)
+        buf, n = make_views(views)
+        h = ctypes.c_void_p()
+        check(_lib.lib().dc_plan_create(ctypes.byref(self.grid), buf, n, 0, ctypes.byref(h)), "dc_plan_create")
+        self.handle = h
+        self.n_views = n
+        g = self.grid
+        self.det_shape = (g.nv, g.nu)
+        self.sino_shape = (g.n_theta, g.n_s)
+        self.vol_shape = (g.nz, g.ny, g.nx)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().dc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, name, shape, dtypes=(torch.float32,), nullable=False):
+    if t is None:
+        if nullable:
+            return
+        raise ValueError("%s is required" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if t.dtype not in dtypes:
+        raise ValueError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _range(plan, v0, nv):
+    if nv is None:
+        nv = plan.n_views - v0
+    return int(v0), int(nv)
+
+
+ANY = tuple(_DT)
+
+
+def dc_weight_radon(plan, g, R, v0=0, nv=None, stream=None):
+    V = plan.n_views
+    _need(g, "g", (V,) + plan.det_shape)
+    _need(R, "R", (V,) + plan.sino_shape, ANY)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_weight_radon(plan.handle, _ptr(g), _ptr(R), _DT[R.dtype], v0, nv, _stream(stream)),
+          "dc_weight_radon")
+    return R
+
+
+def dc_weight_radon_adjoint(plan, GR, Gg, v0=0, nv=None, stream=None):
+    V = plan.n_views
+    _need(GR, "GR", (V,) + plan.sino_shape, ANY)
+    _need(Gg, "Gg", (V,) + plan.det_shape)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_weight_radon_adjoint(plan.handle, _ptr(GR), _DT[GR.dtype], _ptr(Gg), v0, nv,
+                                             _stream(stream)), "dc_weight_radon_adjoint")
+    return Gg
+
+
+def dc_filter(plan, R, M, H, mode="analytic", v0=0, nv=None, stream=None):
+    V = plan.n_views
+    _need(R, "R", (V,) + plan.sino_shape, ANY)
+    _need(M, "M", (V,) + plan.sino_shape)
+    _need(H, "H", (V,) + plan.sino_shape, ANY)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_filter(plan.handle, _ptr(R), _DT[R.dtype], _ptr(M), MODES[mode], _ptr(H), _DT[H.dtype],
+                               v0, nv, _stream(stream)), "dc_filter")
+    return H
+
+
+def dc_filter_adjoint(plan, GH, R, M, GM=None, GR=None, mode="analytic", accumulate_GM=False, v0=0, nv=None,
+                      stream=None):
+    V = plan.n_views
+    _need(GH, "GH", (V,) + plan.sino_shape, ANY)
+    _need(R, "R", (V,) + plan.sino_shape, ANY)
+    _need(M, "M", (V,) + plan.sino_shape)
+    _need(GM, "GM", (V,) + plan.sino_shape, nullable=True)
+    _need(GR, "GR", (V,) + plan.sino_shape, nullable=True)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_filter_adjoint(plan.handle, _ptr(GH), _DT[GH.dtype], _ptr(R), _DT[R.dtype], _ptr(M),
+                                       MODES[mode], _ptr(GM), int(bool(accumulate_GM)), _ptr(GR), v0, nv,
+                                       _stream(stream)), "dc_filter_adjoint")
+    return GM, GR
+
+
+def dc_detector_bp(plan, H, gF, v0=0, nv=None, stream=None):
+    V = plan.n_views
+    _need(H, "H", (V,) + plan.sino_shape, ANY)
+    _need(gF, "gF", (V,) + plan.det_shape, ANY)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_detector_bp(plan.handle, _ptr(H), _DT[H.dtype], _ptr(gF), _DT[gF.dtype], v0, nv,
+                                    _stream(stream)), "dc_detector_bp")
+    return gF
+
+
+def dc_detector_bp_adjoint(plan, GgF, GH, v0=0, nv=None, stream=None):
+    V = plan.n_views
+    _need(GgF, "GgF", (V,) + plan.det_shape, ANY)
+    _need(GH, "GH", (V,) + plan.sino_shape, ANY)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_detector_bp_adjoint(plan.handle, _ptr(GgF), _DT[GgF.dtype], _ptr(GH), _DT[GH.dtype], v0,
+                                            nv, _stream(stream)), "dc_detector_bp_adjoint")
+    return GH
+
+
+def dc_cone_bp(plan, gF, f, accumulate=False, relu=False, v0=0, nv=None, stream=None):
+    V = plan.n_views
+    _need(gF, "gF", (V,) + plan.det_shape, ANY)
+    _need(f, "f", plan.vol_shape)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_cone_bp(plan.handle, _ptr(gF), _DT[gF.dtype], _ptr(f), int(bool(accumulate)),
+                                int(bool(relu)), v0, nv, _stream(stream)), "dc_cone_bp")
+    return f
+
+
+def dc_cone_bp_adjoint(plan, Gf, GgF, f_relu=None, v0=0, nv=None, stream=None):
+    V = plan.n_views
+    _need(Gf, "Gf", plan.vol_shape)
+    _need(f_relu, "f_relu", plan.vol_shape, nullable=True)
+    _need(GgF, "GgF", (V,) + plan.det_shape, ANY)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_cone_bp_adjoint(plan.handle, _ptr(Gf), _ptr(f_relu), _ptr(GgF), _DT[GgF.dtype], v0, nv,
+                                        _stream(stream)), "dc_cone_bp_adjoint")
+    return GgF

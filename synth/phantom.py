@@ -160,3 +160,23 @@ def voxelize_gaussian_blobs(blobs, grid):
     for c, s, a in zip(C, S, A):
         out += a * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / (2 * s * s))
     return out
+
+
+def voxelize_torch(ell: Ellipsoids, grid, device="cpu", dtype=torch.float32, z_chunk=16):
+    """Same point-sampled phantom as ``voxelize`` computed with torch (for large volumes)."""
+    dev = torch.device(device)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    xs = (torch.arange(grid.nx, dtype=torch.float64, device=dev) - (grid.nx - 1) / 2) * grid.vx + grid.ox
+    ys = (torch.arange(grid.ny, dtype=torch.float64, device=dev) - (grid.ny - 1) / 2) * grid.vy + grid.oy
+    zs = (torch.arange(grid.nz, dtype=torch.float64, device=dev) - (grid.nz - 1) / 2) * grid.vz + grid.oz
+    out = torch.zeros((grid.nz, grid.ny, grid.nx), dtype=dtype, device=dev)
+    C, A, R, rho = t(ell.centers), t(ell.axes), t(ell.rot), t(ell.density)
+    for z0 in range(0, grid.nz, z_chunk):
+        Z, Y, X = torch.meshgrid(zs[z0:z0 + z_chunk], ys, xs, indexing="ij")
+        Pt = torch.stack([X, Y, Z], dim=-1)
+        acc = torch.zeros(Z.shape, dtype=torch.float64, device=dev)
+        for k in range(C.shape[0]):
+            u = ((Pt - C[k]) @ R[k]) / A[k]
+            acc += rho[k] * ((u * u).sum(-1) <= 1.0)
+        out[z0:z0 + z_chunk] = acc.to(dtype)
+    return out
