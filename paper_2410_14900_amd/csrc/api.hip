@@ -97,8 +97,29 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
 
   // Radon work list: runs of angles whose pixels spread fastest along rows
   // (|A| >= |B|, lanes walk i) or along columns (lanes walk j), cut into chunks.
-  const int kc = std::max(1, std::min(16, 16384 / g->n_s));
+  // LDS holds kc rows of (n_s + 1) 64-bit accumulators (<= 64 KiB)
+  const int kc = std::max(1, std::min(16, 8192 / (g->n_s + 1)));
   p->splat_kc = kc;
+  // bound on pixels sharing one bin on one angle, and whether every pixel's
+  // bin index stays in [-1, n_s - 1] (then the splat needs no range checks)
+  {
+    int max_terms = 1;
+    bool inside = true;
+    for (int kk = 0; kk < K; ++kk) {
+      const double A = std::fabs(ang[3 * kk]), B = std::fabs(ang[3 * kk + 1]);
+      const double per_row = A > 0 ? std::floor(1.0 / A) + 1 : 1e30;
+      const double per_col = B > 0 ? std::floor(1.0 / B) + 1 : 1e30;
+      const double terms = std::min(per_row * g->nv, per_col * g->nu);
+      max_terms = std::max(max_terms, (int)std::min(terms, (double)g->nu * g->nv));
+      for (int c = 0; c < 4; ++c) {
+        const double t = ang[3 * kk + 2] + ((c & 1) ? (g->nu - 1) * ang[3 * kk] : 0.0) +
+                         ((c & 2) ? (g->nv - 1) * ang[3 * kk + 1] : 0.0);
+        if (!(t >= -0.999 && t < g->n_s - 0.001)) inside = false;
+      }
+    }
+    p->splat_max_terms = max_terms;
+    p->splat_checked = inside ? 0 : 1;
+  }
   std::vector<int> chunks;
   for (int kk = 0; kk < K;) {
     int colmajor = std::fabs(ang[3 * kk + 1]) > std::fabs(ang[3 * kk]) ? 1 : 0;

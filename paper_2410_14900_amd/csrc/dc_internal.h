@@ -67,6 +67,8 @@ struct Plan {
   int4* d_chunks = nullptr;      // (k0, count, column_major, 0)
   int n_chunks = 0;
   int splat_kc = 0;              // max angles per chunk
+  int splat_max_terms = 0;       // max pixels that share one (angle, bin)
+  int splat_checked = 1;         // 0 when every pixel lands on bins [-1, n_s) for all angles
   int interp_wl = 0;             // LDS window length for the interpolating kernels
 };
 

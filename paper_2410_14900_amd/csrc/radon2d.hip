@@ -12,36 +12,64 @@ namespace dc {
 
 // ------------------------------------------------------------------ splat
 // One workgroup owns one view and a chunk of <= kc angles whose sinogram rows
-// live in LDS.  Every pixel of the view is read once per chunk and deposits its
-// two hat-function weights with LDS float atomics; rows are then written out
-// once (no global atomics).  For angles closer to the detector rows the lanes of
-// a wave walk along i, otherwise along j, so that neighbouring lanes fall into
-// different bins and LDS atomics rarely collide.
+// live in LDS.  Every pixel of the view is read once per chunk.  Pixel p with
+// fractional bin t = m + f deposits x(1-f) on bin m and x f on bin m+1, i.e.
+//     R(m) = a(m) - b(m) + b(m-1),   a(m) = sum_{m_p = m} x_p,  b(m) = sum_{m_p = m} x_p f_p,
+// so both sums land on the SAME index m_p.  They are accumulated as fixed-point
+// integers packed into one 64-bit word (a + 2^32 b) with a single LDS integer
+// atomic per pixel-angle (float LDS atomics are ~30x slower on this GPU, integer
+// ones run at full LDS rate).  Integer addition is associative, so the result is
+// bit-reproducible.  The fixed-point scale is per workgroup: a first pass finds
+// max|x| over the view and sizes the quantum so that no bin's a-sum can leave
+// 32 bits (at most `max_terms` pixels share a bin on one angle).
 //
 // The fractional bin t reaches ~n_s, where a float32 ulp is 1e-4 bin, so t is
 // formed in float64 (full-rate FMA on CDNA) and only the fraction is rounded.
-template <typename Tin, typename Tout, bool WCOS>
+template <typename Tin, typename Tout, bool WCOS, bool CHECKED>
 __global__ __launch_bounds__(256) void k_splat(const Tin* __restrict__ img, Tout* __restrict__ out, KGrid g,
                                                const int4* __restrict__ chunks,
                                                const double* __restrict__ angd,
-                                               const float4* __restrict__ viewf, float scale, int v0) {
-  extern __shared__ float rows[];
+                                               const float4* __restrict__ viewf, float scale, int v0,
+                                               int max_terms) {
+  extern __shared__ unsigned long long acc[];   // [kn][n_s + 1], index m + 1
   __shared__ double sA[16], sB[16], sC[16];
+  __shared__ float sMax[256];
   const int4 ch = chunks[blockIdx.x];
   const int v = v0 + blockIdx.y;
   const int k0 = ch.x, kn = ch.y, colmajor = ch.z;
-  const int ns = g.n_s;
-  for (int q = threadIdx.x; q < kn * ns; q += blockDim.x) rows[q] = 0.f;
+  const int ns = g.n_s, row = ns + 1;
+  const int npix = g.nu * g.nv;
+  const Tin* im = img + (size_t)v * npix;
+  const float D = viewf[v].x;
+  for (int q = threadIdx.x; q < kn * row; q += blockDim.x) acc[q] = 0ull;
   if (threadIdx.x < kn) {
     const int k = k0 + threadIdx.x;
     sA[threadIdx.x] = angd[3 * k];
     sB[threadIdx.x] = angd[3 * k + 1];
     sC[threadIdx.x] = angd[3 * k + 2];
   }
+  // pass 1: max |x| over the view (x includes the cosine weight)
+  float mx = 0.f;
+  for (int q = threadIdx.x; q < npix; q += blockDim.x) {
+    float x = to_f32(im[q]);
+    if (WCOS) {
+      const int j = q / g.nu, i = q - j * g.nu;
+      const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
+      x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+    }
+    mx = fmaxf(mx, fabsf(x));
+  }
+  sMax[threadIdx.x] = mx;
   __syncthreads();
-  const int npix = g.nu * g.nv;
-  const Tin* im = img + (size_t)v * npix;
-  const float D = viewf[v].x;
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sMax[threadIdx.x] = fmaxf(sMax[threadIdx.x], sMax[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const float vmax = sMax[0];
+  // quantum: |a| per bin stays below 2^31 - 1 with max_terms contributions
+  const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
+  const float S = vmax > 0.f ? qmax / vmax : 0.f;
+  // pass 2: deposit
   for (int q = threadIdx.x; q < npix; q += blockDim.x) {
     int i, j;
     if (colmajor) {
@@ -53,24 +81,37 @@ __global__ __launch_bounds__(256) void k_splat(const Tin* __restrict__ img, Tout
     }
     float x = to_f32(im[j * g.nu + i]);
     if (WCOS) {
-      float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
+      const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
       x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
     }
+    const float xs = x * S;
+    const int qa = (int)rintf(xs);
+    const unsigned sa = (unsigned)(qa >> 31);        // sign extension of qa into the high word
     const double di = (double)i, dj = (double)j;
     for (int kk = 0; kk < kn; ++kk) {
-      double t = fma(di, sA[kk], fma(dj, sB[kk], sC[kk]));
-      double fl = floor(t);
-      int m = (int)fl;
-      float w1 = x * (float)(t - fl);
-      float w0 = x - w1;
-      float* r = rows + kk * ns;
-      if ((unsigned)m < (unsigned)ns) atomicAdd(r + m, w0);
-      if ((unsigned)(m + 1) < (unsigned)ns) atomicAdd(r + m + 1, w1);
+      const double t = fma(di, sA[kk], fma(dj, sB[kk], sC[kk]));
+      const double fl = floor(t);
+      const int m = (int)fl;
+      const int qb = (int)rintf(xs * (float)(t - fl));
+      const unsigned long long word =
+          ((unsigned long long)((unsigned)qb + sa) << 32) | (unsigned long long)(unsigned)qa;
+      if (!CHECKED || (unsigned)(m + 1) <= (unsigned)ns) atomicAdd(acc + kk * row + m + 1, word);
     }
   }
   __syncthreads();
+  // decode: word = a + 2^32 b with |a| < 2^31
   Tout* o = out + ((size_t)v * g.n_theta + k0) * ns;
-  for (int q = threadIdx.x; q < kn * ns; q += blockDim.x) o[q] = from_f32<Tout>(scale * rows[q]);
+  const double inv = S > 0.f ? (double)scale / (double)S : 0.0;
+  for (int q = threadIdx.x; q < kn * ns; q += blockDim.x) {
+    const int kk = q / ns, m = q - kk * ns;
+    const long long w = (long long)acc[kk * row + m + 1];
+    const long long a = (long long)(int)(unsigned)(w & 0xffffffffll);
+    const long long b = (w - a) >> 32;
+    const long long wp = (long long)acc[kk * row + m];
+    const long long ap = (long long)(int)(unsigned)(wp & 0xffffffffll);
+    const long long bp = (wp - ap) >> 32;
+    o[q] = from_f32<Tout>((float)((double)(a - b + bp) * inv));
+  }
 }
 
 // ----------------------------------------------------------------- interp
@@ -154,18 +195,21 @@ __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, To
 
 hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale, void* out,
                         dc_dtype t_out, int v0, int nv, hipStream_t s) {
-  const size_t lds = (size_t)p.splat_kc * p.kg.n_s * sizeof(float);
+  const size_t lds = (size_t)p.splat_kc * (p.kg.n_s + 1) * sizeof(unsigned long long);
   dim3 grid(p.n_chunks, nv);
   return by_dtype(t_in, [&](auto tin) {
     using Tin = decltype(tin);
     return by_dtype(t_out, [&](auto tout) {
       using Tout = decltype(tout);
-      if (wcos)
-        hipLaunchKernelGGL((k_splat<Tin, Tout, true>), grid, dim3(256), lds, s, (const Tin*)img, (Tout*)out, p.kg,
-                           p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0);
-      else
-        hipLaunchKernelGGL((k_splat<Tin, Tout, false>), grid, dim3(256), lds, s, (const Tin*)img, (Tout*)out, p.kg,
-                           p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0);
+#define DC_SPLAT(W, C)                                                                                         \
+  hipLaunchKernelGGL((k_splat<Tin, Tout, W, C>), grid, dim3(256), lds, s, (const Tin*)img, (Tout*)out, p.kg,  \
+                     p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, p.splat_max_terms)
+      if (wcos) {
+        if (p.splat_checked) DC_SPLAT(true, true); else DC_SPLAT(true, false);
+      } else {
+        if (p.splat_checked) DC_SPLAT(false, true); else DC_SPLAT(false, false);
+      }
+#undef DC_SPLAT
       return hipGetLastError();
     });
   });
