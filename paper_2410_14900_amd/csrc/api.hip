@@ -131,8 +131,9 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
   }
   p->n_chunks = (int)chunks.size() / 4;
 
-  std::vector<float> vf(4 * n);
+  std::vector<float> vf(4 * n), rmax2(n);
   std::vector<double> proj(12 * n);
+  double umax_all = 0.0;
   const double X0[3] = {-0.5 * (g->nx - 1) * g->vx + g->ox, -0.5 * (g->ny - 1) * g->vy + g->oy,
                         -0.5 * (g->nz - 1) * g->vz + g->oz};
   const double vs[3] = {g->vx, g->vy, g->vz};
@@ -158,10 +159,32 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
     }
     double dn0 = -dot3(rel0, lz) / D;
     P[3] = dn0;
+    // depth range over the box of voxel centres (affine, extremes at corners)
+    double umin = 1e300, umax = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+      double den = dn0;
+      for (int c = 0; c < 3; ++c) {
+        const int nn = c == 0 ? g->nx : c == 1 ? g->ny : g->nz;
+        if (corner & (1 << c)) den += P[c] * (nn - 1);
+      }
+      umin = std::min(umin, den * D);
+      umax = std::max(umax, den * D);
+    }
+    rmax2[v] = (float)((D / umin) * (D / umin) * (1.0 + 1e-6));
+    umax_all = std::max(umax_all, umax / D);
     P[7] = dot3(rel0, w.ex) / g->du + 0.5 * (g->nu - 1) * dn0;
     P[11] = dot3(rel0, w.ey) / g->dv + 0.5 * (g->nv - 1) * dn0;
   }
 
+  // voxels that can share one pixel cell in a view: per slice along any axis the
+  // cell's preimage spans at most sqrt(3) * pitch * U/D in each in-slice direction
+  {
+    const double vmin = std::min(g->vx, std::min(g->vy, g->vz));
+    const double cell = std::sqrt(3.0) * std::max(g->du, g->dv) * umax_all / vmin;
+    const double per_axis = std::ceil(cell) + 1.0;
+    const double n_slices = std::max(g->nx, std::max(g->ny, g->nz));
+    p->cone_max_terms = (int)std::min(1e8, n_slices * per_axis * per_axis);
+  }
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dst, bytes);
     if (e != hipSuccess) return e;
@@ -173,6 +196,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
       (e = up((void**)&p->d_trig, trig.data(), trig.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_view, vf.data(), vf.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
+      (e = up((void**)&p->d_rmax2, rmax2.data(), rmax2.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess)
     return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP,
                 std::string("plan upload: ") + hipGetErrorString(e));
@@ -180,7 +204,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
 }
 
 static void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_ang, p->d_angf, p->d_trig, p->d_view, p->d_proj, p->d_chunks};
+  void* ptrs[] = {p->d_ang, p->d_angf, p->d_trig, p->d_view, p->d_proj, p->d_rmax2, p->d_chunks};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -367,7 +391,6 @@ dc_status dc_cone_bp_adjoint(dc_plan plan, const float* Gf, const float* f_relu,
   DC_TRY(check_ptr(f_relu, "f_relu", true));
   DC_TRY(check_ptr(GgF, "GgF"));
   DC_TRY(check_dtype(tF, "GgF"));
-  if (tF != DC_F32) return fail(DC_ENOTSUP, "dc_cone_bp_adjoint: GgF must be float32");
   if (nv == 0) return DC_OK;
   const Plan& p = *reinterpret_cast<Plan*>(plan);
   return launched(launch_cone_fp(p, Gf, f_relu, GgF, tF, v0, nv, stream), "dc_cone_bp_adjoint");

@@ -7,7 +7,7 @@
 // with the per-view projective map i* = num_u/den, j* = num_v/den, den = U/D,
 // all affine in the voxel index (float64 table built by the plan).
 //
-// Work mapping: a thread owns one (x, y) voxel column segment of kZC voxels and
+// Backprojection work mapping: a thread owns one (x, y) voxel column segment of kZC voxels and
 // walks it in z; lanes of a wave are consecutive x, so volume reads and writes
 // are coalesced.  For every view the thread forms its column's projection
 // coefficients in float64 relative to an integer detector origin near the
@@ -89,59 +89,210 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
   }
 }
 
-__global__ void k_fill_zero(float* __restrict__ p, size_t n) {
-  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
-    p[q] = 0.f;
+// ------------------------------------------------------------- transpose
+// Gather form of the transpose, without global atomics: one workgroup owns one
+// 16 x 64 pixel tile of one view and visits every voxel whose bilinear footprint
+// touches it, i.e. i* in [i0-1, i1), j* in [j0-1, j1).  In voxel-index space these
+// are four half-spaces L_k(x) >= 0 (affine because the projection is
+// projective with a positive denominator).  The voxels are enumerated as
+// x-runs of 8-voxel z-segments: every (z-segment, y) row of the volume is
+// intersected with the four half-spaces (a conservative x-interval; the exact
+// test is made per voxel), the non-empty rows are compacted into an LDS list,
+// and a flattened index over the list gives every lane one (x, y, z-segment)
+// item, walked in z like the backprojection.
+//
+// A voxel with fractional projection (ib + fu, jb + fv) and weight g adds
+// g(1-fu)(1-fv), g fu(1-fv), g(1-fu)fv, g fu fv to its four taps.  The four sums
+// A = sum g, B = sum g fu, C = sum g fv, E = sum g fu fv are kept at index
+// (ib, jb) as fixed-point integers packed two per 64-bit word and added with
+// LDS integer atomics; the tile is decoded at the end as
+//   out(i,j) = A - B - C + E |(i,j) + (B - E)|(i-1,j) + (C - E)|(i,j-1) + E|(i-1,j-1).
+// Integer sums make the result bit-reproducible.  The fixed-point quantum comes
+// from a first pass over the same items (max |Gf|) and the per-view bound on
+// (D/U)^2, sized so no index's sums leave 32 bits.
+static constexpr int kFTI = 16, kFTJ = 64, kFZS = 8, kFROWS = 1024;
+static constexpr int kFW = kFTI + 1, kFH = kFTJ + 1;
+
+__device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
+  // inclusive Hillis-Steele over 256 threads in LDS, returns the exclusive prefix
+  const int t = threadIdx.x;
+  tmp[t] = v;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    int add = t >= d ? tmp[t - d] : 0;
+    __syncthreads();
+    tmp[t] += add;
+    __syncthreads();
+  }
+  int incl = tmp[t];
+  __syncthreads();
+  return incl - v;
 }
 
-// Scatter form of the transpose: each voxel adds its four weighted taps to the
-// view's detector image with global float atomics.
-__global__ __launch_bounds__(256) void k_cone_fp_scatter(const float* __restrict__ Gf,
-                                                         const float* __restrict__ f_relu,
-                                                         float* __restrict__ GgF, KGrid g,
-                                                         const double* __restrict__ proj, int v0, int nv) {
-  const int ix = blockIdx.x * kBX + threadIdx.x;
-  const int iy = blockIdx.y * kBY + threadIdx.y;
-  const int iz0 = blockIdx.z * kZC;
-  float gv[kZC];
-  const bool col_ok = ix < g.nx && iy < g.ny;
-#pragma unroll
-  for (int z = 0; z < kZC; ++z) {
-    const int iz = iz0 + z;
-    float x = 0.f;
-    if (col_ok && iz < g.nz) {
-      const size_t o = ((size_t)iz * g.ny + iy) * g.nx + ix;
-      x = Gf[o];
-      if (f_relu && !(f_relu[o] > 0.f)) x = 0.f;
-    }
-    gv[z] = x;
+template <typename Tout>
+__global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, const float* __restrict__ f_relu,
+                                                 Tout* __restrict__ GgF, KGrid g, const double* __restrict__ proj,
+                                                 const float* __restrict__ rmax2, int v0, int tiles_u,
+                                                 int max_terms) {
+  __shared__ double sL[4][4], sNegInvA[4];
+  __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
+  __shared__ int sScan[256];
+  __shared__ int sCount;
+  __shared__ float sRed[256];
+  __shared__ unsigned long long sAB[kFW * kFH], sCE[kFW * kFH];
+  const int v = v0 + blockIdx.y;
+  const int ti = blockIdx.x % tiles_u, tj = blockIdx.x / tiles_u;
+  const int i0 = ti * kFTI, i1 = min(g.nu, i0 + kFTI);
+  const int j0 = tj * kFTJ, j1 = min(g.nv, j0 + kFTJ);
+  const double* P = proj + 12 * v;
+  if (threadIdx.x < 16) {
+    const int k = threadIdx.x >> 2, c = threadIdx.x & 3;
+    const double den = P[c], nu = P[4 + c], nvv = P[8 + c];
+    double val;
+    if (k == 0) val = nu - (i0 - 1) * den;        // i* >= i0 - 1
+    else if (k == 1) val = i1 * den - nu;         // i* <  i1
+    else if (k == 2) val = nvv - (j0 - 1) * den;  // j* >= j0 - 1
+    else val = j1 * den - nvv;                    // j* <  j1
+    sL[k][c] = val;
+    if (c == 0) sNegInvA[k] = val != 0.0 ? -1.0 / val : 0.0;
   }
-  const size_t npix = (size_t)g.nu * g.nv;
-  for (int v = v0; v < v0 + nv; ++v) {
-    const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
-    float* img = GgF + (size_t)v * npix;
+  for (int q = threadIdx.x; q < kFW * kFH; q += blockDim.x) {
+    sAB[q] = 0ull;
+    sCE[q] = 0ull;
+  }
+  __syncthreads();
+  const int nzs = (g.nz + kFZS - 1) / kFZS;
+  const int nrows = nzs * g.ny;
+  const size_t plane = (size_t)g.nx * g.ny;
+  float S = 0.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    float mx = 0.f;
+    for (int r0 = 0; r0 < nrows; r0 += kFROWS) {
+      if (threadIdx.x == 0) sCount = 0;
+      __syncthreads();
+      // 1. rows of this batch whose x-interval may meet the frustum
+      for (int r = r0 + threadIdx.x; r < min(nrows, r0 + kFROWS); r += blockDim.x) {
+        const int zs = r / g.ny, iy = r - zs * g.ny;
+        const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
+        double xlo = 0.0, xhi = g.nx - 1;
+        bool empty = false;
 #pragma unroll
-    for (int z = 0; z < kZC; ++z) {
-      if (gv[z] == 0.f) continue;
-      const float den = fmaf((float)z, c.dden, c.den);
-      const float r = __builtin_amdgcn_rcpf(den);
-      const float u = fmaf((float)z, c.ldu, c.lu) * r;
-      const float w = fmaf((float)z, c.ldv, c.lv) * r;
-      const float fu0 = floorf(u), fw0 = floorf(w);
-      const float fu = u - fu0, fw = w - fw0;
-      const int i = c.iu0 + (int)fu0, j = c.jv0 + (int)fw0;
-      const float s = r * r * gv[z];
-      const float b0 = s * (1.f - fw), b1 = s * fw;
-      const bool i0ok = (unsigned)i < (unsigned)g.nu, i1ok = (unsigned)(i + 1) < (unsigned)g.nu;
-      if ((unsigned)j < (unsigned)g.nv) {
-        if (i0ok) atomicAdd(img + j * g.nu + i, b0 * (1.f - fu));
-        if (i1ok) atomicAdd(img + j * g.nu + i + 1, b0 * fu);
+        for (int k = 0; k < 4; ++k) {
+          const double a = sL[k][0];
+          const double c0 = fma(sL[k][1], (double)iy, sL[k][3]);
+          const double cm = fmax(fma(sL[k][2], zlo, c0), fma(sL[k][2], zhi, c0));
+          const double xb = cm * sNegInvA[k];      // L_k = a x + cm crosses zero here
+          if (a > 0.0) xlo = fmax(xlo, ceil(xb) - 1.0);
+          else if (a < 0.0) xhi = fmin(xhi, floor(xb) + 1.0);
+          else if (cm < 0.0) empty = true;
+        }
+        if (!empty && xlo <= xhi) {
+          const int slot = atomicAdd(&sCount, 1);
+          sRow[slot] = r;
+          sXlo[slot] = (int)xlo;
+          sPre[slot] = (int)(xhi - xlo) + 1;   // length for now
+        }
       }
-      if ((unsigned)(j + 1) < (unsigned)g.nv) {
-        if (i0ok) atomicAdd(img + (j + 1) * g.nu + i, b1 * (1.f - fu));
-        if (i1ok) atomicAdd(img + (j + 1) * g.nu + i + 1, b1 * fu);
+      __syncthreads();
+      const int cnt = sCount;
+      // 2. exclusive prefix of the run lengths (4 entries per thread)
+      int loc[4], sum = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x * 4 + e;
+        loc[e] = idx < cnt ? sPre[idx] : 0;
+        sum += loc[e];
       }
+      int run = block_exclusive_scan_256(sum, sScan);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x * 4 + e;
+        if (idx < cnt) sPre[idx] = run;
+        run += loc[e];
+      }
+      if (threadIdx.x == 255) sPre[cnt] = run;   // total (thread 255 holds the last entries)
+      __syncthreads();
+      const int total = sPre[cnt];
+      // 3. flattened items: (row, x) -> an 8-voxel z-segment
+      for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {                       // last row with sPre[row] <= q
+          const int mid = (lo + hi + 1) >> 1;
+          if (sPre[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const int r = sRow[lo];
+        const int ix = sXlo[lo] + (q - sPre[lo]);
+        const int zs = r / g.ny, iy = r - zs * g.ny;
+        const int iz0 = zs * kFZS;
+        const int nzv = min(kFZS, g.nz - iz0);
+        const size_t base = (size_t)iz0 * plane + (size_t)iy * g.nx + ix;
+        if (pass == 0) {
+          for (int z = 0; z < nzv; ++z) {
+            float x = Gf[base + z * plane];
+            if (f_relu && !(f_relu[base + z * plane] > 0.f)) x = 0.f;
+            mx = fmaxf(mx, fabsf(x));
+          }
+        } else {
+          const ColumnMap c = column_map(P, ix, iy, iz0);
+          for (int z = 0; z < nzv; ++z) {
+            float x = Gf[base + z * plane];
+            if (f_relu && !(f_relu[base + z * plane] > 0.f)) x = 0.f;
+            const float den = fmaf((float)z, c.dden, c.den);
+            const float rr = __builtin_amdgcn_rcpf(den);
+            const float u = fmaf((float)z, c.ldu, c.lu) * rr;
+            const float w = fmaf((float)z, c.ldv, c.lv) * rr;
+            const float fu0 = floorf(u), fw0 = floorf(w);
+            const int li = c.iu0 + (int)fu0 - (i0 - 1), lj = c.jv0 + (int)fw0 - (j0 - 1);
+            if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
+              const float fu = u - fu0, fv = w - fw0;
+              const float gs = x * rr * rr * S;
+              const float gu = gs * fu;
+              const int qa = (int)rintf(gs), qb = (int)rintf(gu);
+              const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
+              const unsigned long long w1 =
+                  ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
+              const unsigned long long w2 =
+                  ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
+              atomicAdd(sAB + lj * kFW + li, w1);
+              atomicAdd(sCE + lj * kFW + li, w2);
+            }
+          }
+        }
+      }
+      __syncthreads();
     }
+    if (pass == 0) {
+      sRed[threadIdx.x] = mx;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sRed[threadIdx.x] = fmaxf(sRed[threadIdx.x], sRed[threadIdx.x + w]);
+        __syncthreads();
+      }
+      const float gmax = sRed[0] * rmax2[v];
+      const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
+      S = gmax > 0.f ? qmax / gmax : 0.f;
+      __syncthreads();
+    }
+  }
+  // decode the tile
+  const double inv = S > 0.f ? 1.0 / (double)S : 0.0;
+  auto lo32 = [](unsigned long long w) { return (long long)(int)(unsigned)(w & 0xffffffffull); };
+  auto hi32 = [](unsigned long long w, long long lo) { return ((long long)w - lo) >> 32; };
+  Tout* o = GgF + (size_t)v * g.nu * g.nv;
+  for (int q = threadIdx.x; q < kFTI * kFTJ; q += blockDim.x) {
+    const int di = q % kFTI, dj = q / kFTI;
+    const int i = i0 + di, j = j0 + dj;
+    if (i >= i1 || j >= j1) continue;
+    const int li = di + 1, lj = dj + 1;
+    const unsigned long long ab = sAB[lj * kFW + li], ce = sCE[lj * kFW + li];
+    const unsigned long long abl = sAB[lj * kFW + li - 1], cel = sCE[lj * kFW + li - 1];
+    const unsigned long long ced = sCE[(lj - 1) * kFW + li], celd = sCE[(lj - 1) * kFW + li - 1];
+    const long long A = lo32(ab), B = hi32(ab, A), C = lo32(ce), E = hi32(ce, C);
+    const long long Bl = hi32(abl, lo32(abl)), Cl = lo32(cel), El = hi32(cel, Cl);
+    const long long Cd = lo32(ced), Ed = hi32(ced, Cd);
+    const long long Eld = hi32(celd, lo32(celd));
+    const long long val = A - B - C + E + (Bl - El) + (Cd - Ed) + Eld;
+    o[j * g.nu + i] = from_f32<Tout>((float)((double)val * inv));
   }
 }
 
@@ -158,16 +309,14 @@ hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, 
 
 hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, void* GgF, dc_dtype tF, int v0,
                           int nv, hipStream_t s) {
-  if (tF != DC_F32) return hipErrorNotSupported;
-  float* out = (float*)GgF + (size_t)v0 * p.kg.nu * p.kg.nv;
-  const size_t n = (size_t)nv * p.kg.nu * p.kg.nv;
-  hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(256), 0, s, out, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + kBY - 1) / kBY, (p.kg.nz + kZC - 1) / kZC);
-  hipLaunchKernelGGL(k_cone_fp_scatter, grid, dim3(kBX, kBY), 0, s, Gf, f_relu, (float*)GgF, p.kg, p.d_proj, v0,
-                     nv);
-  return hipGetLastError();
+  const int tiles_u = (p.kg.nu + kFTI - 1) / kFTI, tiles_v = (p.kg.nv + kFTJ - 1) / kFTJ;
+  dim3 grid(tiles_u * tiles_v, nv);
+  return by_dtype(tF, [&](auto t) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((k_cone_fp<T>), grid, dim3(256), 0, s, Gf, f_relu, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
+                       tiles_u, p.cone_max_terms);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace dc

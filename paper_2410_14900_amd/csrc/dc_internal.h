@@ -63,6 +63,8 @@ struct Plan {
   // each with coefficients of (ix, iy, iz, 1); i* = num_u/den, j* = num_v/den,
   // den = U/D, weight (D/U)^2 = 1/den^2
   double* d_proj = nullptr;      // [V][12]
+  float* d_rmax2 = nullptr;      // [V] upper bound of (D/U)^2 over the volume
+  int cone_max_terms = 0;        // max voxels sharing one (pixel cell) index in one view
   // splat (Radon) work list: angle chunks that stay on one side of the diagonal
   int4* d_chunks = nullptr;      // (k0, count, column_major, 0)
   int n_chunks = 0;
