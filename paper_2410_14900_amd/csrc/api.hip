@@ -37,6 +37,7 @@ static dc_status validate(const dc_grid* g, const dc_view* views, int32_t n) {
       (double)g->nx * g->ny * g->nz > lim / 4)
     return fail(DC_ESHAPE, "per-view image, sinogram or volume too large for 32-bit indexing");
   if (g->n_s > 4096) return fail(DC_ESHAPE, "n_s above 4096 not supported (sinogram rows are staged in LDS)");
+  if (g->nz > 1024) return fail(DC_ESHAPE, "nz above 1024 not supported");
   if (!(g->du > 0 && g->dv > 0 && g->ds > 0 && g->vx > 0 && g->vy > 0 && g->vz > 0))
     return fail(DC_EINVAL, "pitches and voxel sizes must be positive");
   const double hx = 0.5 * g->nx * g->vx, hy = 0.5 * g->ny * g->vy, hz = 0.5 * g->nz * g->vz;
@@ -197,14 +198,15 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
       (e = up((void**)&p->d_view, vf.data(), vf.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
       (e = up((void**)&p->d_rmax2, rmax2.data(), rmax2.size() * sizeof(float))) != hipSuccess ||
-      (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess)
+      (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_scratch, (n + 1) * sizeof(unsigned))) != hipSuccess)
     return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP,
                 std::string("plan upload: ") + hipGetErrorString(e));
   return DC_OK;
 }
 
 static void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_ang, p->d_angf, p->d_trig, p->d_view, p->d_proj, p->d_rmax2, p->d_chunks};
+  void* ptrs[] = {p->d_ang, p->d_angf, p->d_trig, p->d_view, p->d_proj, p->d_rmax2, p->d_chunks, p->d_scratch};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;

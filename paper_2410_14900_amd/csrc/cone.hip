@@ -13,6 +13,8 @@
 // coefficients in float64 relative to an integer detector origin near the
 // column's projection, so the float32 per-voxel coordinates stay small and
 // their rounding far below 1e-5 pixel.
+#include <algorithm>
+
 #include "dc_internal.h"
 
 namespace dc {
@@ -108,8 +110,9 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 // LDS integer atomics; the tile is decoded at the end as
 //   out(i,j) = A - B - C + E |(i,j) + (B - E)|(i-1,j) + (C - E)|(i,j-1) + E|(i-1,j-1).
 // Integer sums make the result bit-reproducible.  The fixed-point quantum comes
-// from a first pass over the same items (max |Gf|) and the per-view bound on
-// (D/U)^2, sized so no index's sums leave 32 bits.
+// from max |Gf| (a reduction kernel into the plan's scratch) and the per-view
+// bound on (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
+// box can reach the tile's window are scanned.
 static constexpr int kFTI = 16, kFTJ = 64, kFZS = 8, kFROWS = 1024;
 static constexpr int kFW = kFTI + 1, kFH = kFTJ + 1;
 
@@ -129,16 +132,38 @@ __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
   return incl - v;
 }
 
+// max |Gf * mask| over the volume, as float bits
+__global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf, const float* __restrict__ f_relu,
+                                                    size_t n, unsigned* __restrict__ out) {
+  __shared__ float red[256];
+  float mx = 0.f;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+    float x = Gf[q];
+    if (f_relu && !(f_relu[q] > 0.f)) x = 0.f;
+    mx = fmaxf(mx, fabsf(x));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+static constexpr int kFMaxLayers = 128;
+
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, const float* __restrict__ f_relu,
                                                  Tout* __restrict__ GgF, KGrid g, const double* __restrict__ proj,
                                                  const float* __restrict__ rmax2, int v0, int tiles_u,
-                                                 int max_terms) {
+                                                 int max_terms, const unsigned* __restrict__ gmax_bits) {
   __shared__ double sL[4][4], sNegInvA[4];
   __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
   __shared__ int sScan[256];
-  __shared__ int sCount;
-  __shared__ float sRed[256];
+  __shared__ int sCount, sNL;
+  __shared__ unsigned char sLayerOn[kFMaxLayers];
+  __shared__ int sLayer[kFMaxLayers];
   __shared__ unsigned long long sAB[kFW * kFH], sCE[kFW * kFH];
   const int v = v0 + blockIdx.y;
   const int ti = blockIdx.x % tiles_u, tj = blockIdx.x / tiles_u;
@@ -161,118 +186,120 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
     sCE[q] = 0ull;
   }
   __syncthreads();
+  // z-layers (8 slices each) whose box can reach the window under all four planes
   const int nzs = (g.nz + kFZS - 1) / kFZS;
-  const int nrows = nzs * g.ny;
+  for (int zs = threadIdx.x; zs < nzs; zs += blockDim.x) {
+    const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
+    bool on = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double mxl = fmax(sL[k][0] * 0.0, sL[k][0] * (g.nx - 1)) + fmax(sL[k][1] * 0.0, sL[k][1] * (g.ny - 1)) +
+                         fmax(sL[k][2] * zlo, sL[k][2] * zhi) + sL[k][3];
+      if (mxl < -1e-6 * fabs(sL[k][3]) - 1e-6) on = false;
+    }
+    sLayerOn[zs] = on;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int zs = 0; zs < nzs; ++zs)
+      if (sLayerOn[zs]) sLayer[n++] = zs;
+    sNL = n;
+  }
+  __syncthreads();
+  const int nrows = sNL * g.ny;
   const size_t plane = (size_t)g.nx * g.ny;
-  float S = 0.f;
-  for (int pass = 0; pass < 2; ++pass) {
-    float mx = 0.f;
-    for (int r0 = 0; r0 < nrows; r0 += kFROWS) {
-      if (threadIdx.x == 0) sCount = 0;
-      __syncthreads();
-      // 1. rows of this batch whose x-interval may meet the frustum
-      for (int r = r0 + threadIdx.x; r < min(nrows, r0 + kFROWS); r += blockDim.x) {
-        const int zs = r / g.ny, iy = r - zs * g.ny;
-        const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
-        double xlo = 0.0, xhi = g.nx - 1;
-        bool empty = false;
+  const float gmax = __uint_as_float(*gmax_bits) * rmax2[v];
+  const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
+  const float S = gmax > 0.f ? qmax / gmax : 0.f;
+  for (int r0 = 0; r0 < nrows; r0 += kFROWS) {
+    if (threadIdx.x == 0) sCount = 0;
+    __syncthreads();
+    // 1. rows of this batch whose x-interval may meet the frustum
+    for (int r = r0 + threadIdx.x; r < min(nrows, r0 + kFROWS); r += blockDim.x) {
+      const int li = r / g.ny, iy = r - li * g.ny;
+      const int zs = sLayer[li];
+      const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
+      double xlo = 0.0, xhi = g.nx - 1;
+      bool empty = false;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double a = sL[k][0];
-          const double c0 = fma(sL[k][1], (double)iy, sL[k][3]);
-          const double cm = fmax(fma(sL[k][2], zlo, c0), fma(sL[k][2], zhi, c0));
-          const double xb = cm * sNegInvA[k];      // L_k = a x + cm crosses zero here
-          if (a > 0.0) xlo = fmax(xlo, ceil(xb) - 1.0);
-          else if (a < 0.0) xhi = fmin(xhi, floor(xb) + 1.0);
-          else if (cm < 0.0) empty = true;
-        }
-        if (!empty && xlo <= xhi) {
-          const int slot = atomicAdd(&sCount, 1);
-          sRow[slot] = r;
-          sXlo[slot] = (int)xlo;
-          sPre[slot] = (int)(xhi - xlo) + 1;   // length for now
-        }
+      for (int k = 0; k < 4; ++k) {
+        const double a = sL[k][0];
+        const double c0 = fma(sL[k][1], (double)iy, sL[k][3]);
+        const double cm = fmax(fma(sL[k][2], zlo, c0), fma(sL[k][2], zhi, c0));
+        const double xb = cm * sNegInvA[k];      // L_k = a x + cm crosses zero here
+        if (a > 0.0) xlo = fmax(xlo, ceil(xb) - 1.0);
+        else if (a < 0.0) xhi = fmin(xhi, floor(xb) + 1.0);
+        else if (cm < 0.0) empty = true;
       }
-      __syncthreads();
-      const int cnt = sCount;
-      // 2. exclusive prefix of the run lengths (4 entries per thread)
-      int loc[4], sum = 0;
+      if (!empty && xlo <= xhi) {
+        const int slot = atomicAdd(&sCount, 1);
+        sRow[slot] = zs * g.ny + iy;
+        sXlo[slot] = (int)xlo;
+        sPre[slot] = (int)(xhi - xlo) + 1;   // length for now
+      }
+    }
+    __syncthreads();
+    const int cnt = sCount;
+    // 2. exclusive prefix of the run lengths (4 entries per thread)
+    int loc[4], sum = 0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int idx = threadIdx.x * 4 + e;
-        loc[e] = idx < cnt ? sPre[idx] : 0;
-        sum += loc[e];
-      }
-      int run = block_exclusive_scan_256(sum, sScan);
+    for (int e = 0; e < 4; ++e) {
+      const int idx = threadIdx.x * 4 + e;
+      loc[e] = idx < cnt ? sPre[idx] : 0;
+      sum += loc[e];
+    }
+    int run = block_exclusive_scan_256(sum, sScan);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int idx = threadIdx.x * 4 + e;
-        if (idx < cnt) sPre[idx] = run;
-        run += loc[e];
+    for (int e = 0; e < 4; ++e) {
+      const int idx = threadIdx.x * 4 + e;
+      if (idx < cnt) sPre[idx] = run;
+      run += loc[e];
+    }
+    if (threadIdx.x == 255) sPre[cnt] = run;   // total (thread 255 holds the last entries)
+    __syncthreads();
+    const int total = sPre[cnt];
+    // 3. flattened items: (row, x) -> an 8-voxel z-segment
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      int lo = 0, hi = cnt - 1;
+      while (lo < hi) {                       // last row with sPre[row] <= q
+        const int mid = (lo + hi + 1) >> 1;
+        if (sPre[mid] <= q) lo = mid; else hi = mid - 1;
       }
-      if (threadIdx.x == 255) sPre[cnt] = run;   // total (thread 255 holds the last entries)
-      __syncthreads();
-      const int total = sPre[cnt];
-      // 3. flattened items: (row, x) -> an 8-voxel z-segment
-      for (int q = threadIdx.x; q < total; q += blockDim.x) {
-        int lo = 0, hi = cnt - 1;
-        while (lo < hi) {                       // last row with sPre[row] <= q
-          const int mid = (lo + hi + 1) >> 1;
-          if (sPre[mid] <= q) lo = mid; else hi = mid - 1;
-        }
-        const int r = sRow[lo];
-        const int ix = sXlo[lo] + (q - sPre[lo]);
-        const int zs = r / g.ny, iy = r - zs * g.ny;
-        const int iz0 = zs * kFZS;
-        const int nzv = min(kFZS, g.nz - iz0);
-        const size_t base = (size_t)iz0 * plane + (size_t)iy * g.nx + ix;
-        if (pass == 0) {
-          for (int z = 0; z < nzv; ++z) {
-            float x = Gf[base + z * plane];
-            if (f_relu && !(f_relu[base + z * plane] > 0.f)) x = 0.f;
-            mx = fmaxf(mx, fabsf(x));
-          }
-        } else {
-          const ColumnMap c = column_map(P, ix, iy, iz0);
-          for (int z = 0; z < nzv; ++z) {
-            float x = Gf[base + z * plane];
-            if (f_relu && !(f_relu[base + z * plane] > 0.f)) x = 0.f;
-            const float den = fmaf((float)z, c.dden, c.den);
-            const float rr = __builtin_amdgcn_rcpf(den);
-            const float u = fmaf((float)z, c.ldu, c.lu) * rr;
-            const float w = fmaf((float)z, c.ldv, c.lv) * rr;
-            const float fu0 = floorf(u), fw0 = floorf(w);
-            const int li = c.iu0 + (int)fu0 - (i0 - 1), lj = c.jv0 + (int)fw0 - (j0 - 1);
-            if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
-              const float fu = u - fu0, fv = w - fw0;
-              const float gs = x * rr * rr * S;
-              const float gu = gs * fu;
-              const int qa = (int)rintf(gs), qb = (int)rintf(gu);
-              const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
-              const unsigned long long w1 =
-                  ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
-              const unsigned long long w2 =
-                  ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
-              atomicAdd(sAB + lj * kFW + li, w1);
-              atomicAdd(sCE + lj * kFW + li, w2);
-            }
+      const int r = sRow[lo];
+      const int ix = sXlo[lo] + (q - sPre[lo]);
+      const int zs = r / g.ny, iy = r - zs * g.ny;
+      const int iz0 = zs * kFZS;
+      const int nzv = min(kFZS, g.nz - iz0);
+      const size_t base = (size_t)iz0 * plane + (size_t)iy * g.nx + ix;
+      const ColumnMap c = column_map(P, ix, iy, iz0);
+      for (int z = 0; z < nzv; ++z) {
+        const float den = fmaf((float)z, c.dden, c.den);
+        const float rr = __builtin_amdgcn_rcpf(den);
+        const float u = fmaf((float)z, c.ldu, c.lu) * rr;
+        const float w = fmaf((float)z, c.ldv, c.lv) * rr;
+        const float fu0 = floorf(u), fw0 = floorf(w);
+        const int li = c.iu0 + (int)fu0 - (i0 - 1), lj = c.jv0 + (int)fw0 - (j0 - 1);
+        if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0)) {
+          float x = Gf[base + z * plane];
+          if (f_relu && !(f_relu[base + z * plane] > 0.f)) x = 0.f;
+          if (x != 0.f) {
+            const float fu = u - fu0, fv = w - fw0;
+            const float gs = x * rr * rr * S;
+            const float gu = gs * fu;
+            const int qa = (int)rintf(gs), qb = (int)rintf(gu);
+            const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
+            const unsigned long long w1 =
+                ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
+            const unsigned long long w2 =
+                ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
+            atomicAdd(sAB + lj * kFW + li, w1);
+            atomicAdd(sCE + lj * kFW + li, w2);
           }
         }
       }
-      __syncthreads();
     }
-    if (pass == 0) {
-      sRed[threadIdx.x] = mx;
-      __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sRed[threadIdx.x] = fmaxf(sRed[threadIdx.x], sRed[threadIdx.x + w]);
-        __syncthreads();
-      }
-      const float gmax = sRed[0] * rmax2[v];
-      const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
-      S = gmax > 0.f ? qmax / gmax : 0.f;
-      __syncthreads();
-    }
+    __syncthreads();
   }
   // decode the tile
   const double inv = S > 0.f ? 1.0 / (double)S : 0.0;
@@ -310,11 +337,18 @@ hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, 
 hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, void* GgF, dc_dtype tF, int v0,
                           int nv, hipStream_t s) {
   const int tiles_u = (p.kg.nu + kFTI - 1) / kFTI, tiles_v = (p.kg.nv + kFTJ - 1) / kFTJ;
+  unsigned* gmax = p.d_scratch + p.n_views;
+  hipError_t e = launch_zero_u32(gmax, 1, s);
+  if (e != hipSuccess) return e;
+  const size_t n = (size_t)p.kg.nx * p.kg.ny * p.kg.nz;
+  const int blocks = (int)std::min<size_t>(2048, (n + 255) / 256);
+  hipLaunchKernelGGL(k_vol_absmax, dim3(blocks), dim3(256), 0, s, Gf, f_relu, n, gmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   dim3 grid(tiles_u * tiles_v, nv);
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
     hipLaunchKernelGGL((k_cone_fp<T>), grid, dim3(256), 0, s, Gf, f_relu, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
-                       tiles_u, p.cone_max_terms);
+                       tiles_u, p.cone_max_terms, gmax);
     return hipGetLastError();
   });
 }

@@ -67,6 +67,10 @@ struct Plan {
   int cone_max_terms = 0;        // max voxels sharing one (pixel cell) index in one view
   // splat (Radon) work list: angle chunks that stay on one side of the diagonal
   int4* d_chunks = nullptr;      // (k0, count, column_major, 0)
+  // plan-owned scratch: [0, V) per-view max |input| of the splat, [V] max |Gf| of
+  // the cone adjoint (float bits, reduced with integer atomicMax).  Calls on one
+  // plan must therefore be ordered on one stream.
+  unsigned* d_scratch = nullptr; // [V + 1]
   int n_chunks = 0;
   int splat_kc = 0;              // max angles per chunk
   int splat_max_terms = 0;       // max pixels that share one (angle, bin)
@@ -75,6 +79,9 @@ struct Plan {
 };
 
 void set_error(const std::string& msg);
+
+// scratch helpers (radon2d.hip)
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 
 // launchers (return hipSuccess or the launch error)
 hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale,

@@ -6,6 +6,8 @@
 // with t_pk = i A_k + j B_k + C_k the fractional s-bin of pixel p=(i,j) on angle
 // mu_k, Lambda the hat function and w the optional cosine weight D/sqrt(x^2+y^2+D^2).
 // The two are exact transposes of each other for equal scales.
+#include <algorithm>
+
 #include "dc_internal.h"
 
 namespace dc {
@@ -19,21 +21,58 @@ namespace dc {
 // integers packed into one 64-bit word (a + 2^32 b) with a single LDS integer
 // atomic per pixel-angle (float LDS atomics are ~30x slower on this GPU, integer
 // ones run at full LDS rate).  Integer addition is associative, so the result is
-// bit-reproducible.  The fixed-point scale is per workgroup: a first pass finds
-// max|x| over the view and sizes the quantum so that no bin's a-sum can leave
-// 32 bits (at most `max_terms` pixels share a bin on one angle).
+// bit-reproducible.  The fixed-point scale is per view: a small reduction kernel
+// writes max|x| over each view to the plan's scratch, and the quantum is sized so
+// that no bin's a-sum can leave 32 bits (at most `max_terms` pixels share a bin
+// on one angle).
 //
 // The fractional bin t reaches ~n_s, where a float32 ulp is 1e-4 bin, so t is
 // formed in float64 (full-rate FMA on CDNA) and only the fraction is rounded.
+__global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) p[q] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// max |w x| over each view, as float bits (non-negative floats order like their bits)
+template <typename Tin, bool WCOS>
+__global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img, unsigned* __restrict__ vmax, KGrid g,
+                                                     const float4* __restrict__ viewf, int v0) {
+  __shared__ float red[256];
+  const int v = v0 + blockIdx.y;
+  const int npix = g.nu * g.nv;
+  const Tin* im = img + (size_t)v * npix;
+  const float D = viewf[v].x;
+  float mx = 0.f;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npix; q += gridDim.x * blockDim.x) {
+    float x = to_f32(im[q]);
+    if (WCOS) {
+      const int j = q / g.nu, i = q - j * g.nu;
+      const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
+      x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+    }
+    mx = fmaxf(mx, fabsf(x));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(vmax + v, __float_as_uint(red[0]));
+}
+
 template <typename Tin, typename Tout, bool WCOS, bool CHECKED>
-__global__ __launch_bounds__(256) void k_splat(const Tin* __restrict__ img, Tout* __restrict__ out, KGrid g,
+__global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout* __restrict__ out, KGrid g,
                                                const int4* __restrict__ chunks,
                                                const double* __restrict__ angd,
                                                const float4* __restrict__ viewf, float scale, int v0,
-                                               int max_terms) {
+                                               int max_terms, const unsigned* __restrict__ vmax_bits) {
   extern __shared__ unsigned long long acc[];   // [kn][n_s + 1], index m + 1
   __shared__ double sA[16], sB[16], sC[16];
-  __shared__ float sMax[256];
   const int4 ch = chunks[blockIdx.x];
   const int v = v0 + blockIdx.y;
   const int k0 = ch.x, kn = ch.y, colmajor = ch.z;
@@ -48,28 +87,11 @@ __global__ __launch_bounds__(256) void k_splat(const Tin* __restrict__ img, Tout
     sB[threadIdx.x] = angd[3 * k + 1];
     sC[threadIdx.x] = angd[3 * k + 2];
   }
-  // pass 1: max |x| over the view (x includes the cosine weight)
-  float mx = 0.f;
-  for (int q = threadIdx.x; q < npix; q += blockDim.x) {
-    float x = to_f32(im[q]);
-    if (WCOS) {
-      const int j = q / g.nu, i = q - j * g.nu;
-      const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-      x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
-    }
-    mx = fmaxf(mx, fabsf(x));
-  }
-  sMax[threadIdx.x] = mx;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sMax[threadIdx.x] = fmaxf(sMax[threadIdx.x], sMax[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const float vmax = sMax[0];
+  const float vmax = __uint_as_float(vmax_bits[v]);
   // quantum: |a| per bin stays below 2^31 - 1 with max_terms contributions
   const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
   const float S = vmax > 0.f ? qmax / vmax : 0.f;
-  // pass 2: deposit
   for (int q = threadIdx.x; q < npix; q += blockDim.x) {
     int i, j;
     if (colmajor) {
@@ -197,13 +219,24 @@ hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos
                         dc_dtype t_out, int v0, int nv, hipStream_t s) {
   const size_t lds = (size_t)p.splat_kc * (p.kg.n_s + 1) * sizeof(unsigned long long);
   dim3 grid(p.n_chunks, nv);
+  hipError_t e = launch_zero_u32(p.d_scratch + v0, nv, s);
+  if (e != hipSuccess) return e;
   return by_dtype(t_in, [&](auto tin) {
     using Tin = decltype(tin);
+    const int mblocks = std::max(1, std::min(64, (p.kg.nu * p.kg.nv + 4095) / 4096));
+    if (wcos)
+      hipLaunchKernelGGL((k_view_absmax<Tin, true>), dim3(mblocks, nv), dim3(256), 0, s, (const Tin*)img,
+                         p.d_scratch, p.kg, (const float4*)p.d_view, v0);
+    else
+      hipLaunchKernelGGL((k_view_absmax<Tin, false>), dim3(mblocks, nv), dim3(256), 0, s, (const Tin*)img,
+                         p.d_scratch, p.kg, (const float4*)p.d_view, v0);
+    hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) return e2;
     return by_dtype(t_out, [&](auto tout) {
       using Tout = decltype(tout);
 #define DC_SPLAT(W, C)                                                                                         \
-  hipLaunchKernelGGL((k_splat<Tin, Tout, W, C>), grid, dim3(256), lds, s, (const Tin*)img, (Tout*)out, p.kg,  \
-                     p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, p.splat_max_terms)
+  hipLaunchKernelGGL((k_splat<Tin, Tout, W, C>), grid, dim3(512), lds, s, (const Tin*)img, (Tout*)out, p.kg,  \
+                     p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, p.splat_max_terms, p.d_scratch)
       if (wcos) {
         if (p.splat_checked) DC_SPLAT(true, true); else DC_SPLAT(true, false);
       } else {
