@@ -73,6 +73,10 @@ def lib():
     """The loaded library (loaded once).  Raises if it has not been built."""
     global _LIB
     if _LIB is None:
+        # torch ships its own libamdhip64.so.7; loading it first makes this
+        # library bind to the same HIP runtime (same soname) instead of pulling in
+        # a second copy from /opt/rocm, which would leave torch without a device.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError("libdcfbp.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)

@@ -186,6 +186,37 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
     const double n_slices = std::max(g->nx, std::max(g->ny, g->nz));
     p->cone_max_terms = (int)std::min(1e8, n_slices * per_axis * per_axis);
   }
+  // largest backprojection block footprint (same box rule as the kernel) ->
+  // how many pixels each of the 256 threads stages per view
+  {
+    const int B[3] = {cone_bp_block(0), cone_bp_block(1), cone_bp_block(2)};
+    const int nb[3] = {(g->nx + B[0] - 1) / B[0], (g->ny + B[1] - 1) / B[1], (g->nz + B[2] - 1) / B[2]};
+    double worst = 0;
+    for (int v = 0; v < n; ++v) {
+      const double* P = &proj[12 * v];
+      for (int bz = 0; bz < nb[2]; ++bz)
+        for (int by = 0; by < nb[1]; ++by)
+          for (int bx = 0; bx < nb[0]; ++bx) {
+            const int lo[3] = {bx * B[0], by * B[1], bz * B[2]};
+            const int hi[3] = {std::min(g->nx, lo[0] + B[0]) - 1, std::min(g->ny, lo[1] + B[1]) - 1,
+                               std::min(g->nz, lo[2] + B[2]) - 1};
+            double imin = 1e300, imax = -1e300, jmin = 1e300, jmax = -1e300;
+            for (int c = 0; c < 8; ++c) {
+              const double x = (c & 1) ? hi[0] : lo[0], y = (c & 2) ? hi[1] : lo[1], z = (c & 4) ? hi[2] : lo[2];
+              const double den = x * P[0] + y * P[1] + z * P[2] + P[3];
+              const double iu = (x * P[4] + y * P[5] + z * P[6] + P[7]) / den;
+              const double jv = (x * P[8] + y * P[9] + z * P[10] + P[11]) / den;
+              imin = std::min(imin, iu); imax = std::max(imax, iu);
+              jmin = std::min(jmin, jv); jmax = std::max(jmax, jv);
+            }
+            // kernel box: [floor(min)-1, floor(max)+2], plus slack for float rounding
+            const double w = std::floor(imax) - std::floor(imin) + 5, h = std::floor(jmax) - std::floor(jmin) + 5;
+            worst = std::max(worst, w * h);
+          }
+    }
+    const int need = (int)std::ceil(worst / 256.0);
+    p->bp_stage = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 0;
+  }
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dst, bytes);
     if (e != hipSuccess) return e;

@@ -7,9 +7,13 @@
 // with the per-view projective map i* = num_u/den, j* = num_v/den, den = U/D,
 // all affine in the voxel index (float64 table built by the plan).
 //
-// Backprojection work mapping: a thread owns one (x, y) voxel column segment of kZC voxels and
-// walks it in z; lanes of a wave are consecutive x, so volume reads and writes
-// are coalesced.  For every view the thread forms its column's projection
+// Backprojection work mapping: a workgroup owns a 16 x 16 x 16 voxel block and a
+// thread one (x, y) column segment of 16 voxels, walked in z; lanes of a wave
+// cover 16 consecutive x of 4 rows, so volume writes are 64-byte segments.  Per view, the block's
+// detector footprint is staged in LDS (converted to float32 from the storage
+// type) and the taps are LDS reads; the next view's footprint is fetched into
+// registers while the current one is interpolated (double buffering, one barrier
+// per view).  For every view the thread forms its column's projection
 // coefficients in float64 relative to an integer detector origin near the
 // column's projection, so the float32 per-voxel coordinates stay small and
 // their rounding far below 1e-5 pixel.
@@ -19,7 +23,7 @@
 
 namespace dc {
 
-static constexpr int kBX = 64, kBY = 4, kZC = 16;
+static constexpr int kBX = 16, kBY = 16, kZC = 16;
 
 struct ColumnMap {
   float den, dden;   // den = U/D at the segment start and its z step
@@ -50,33 +54,144 @@ __device__ __forceinline__ float tap(const T* __restrict__ img, int i, int j, in
   return ((unsigned)i < (unsigned)nu && (unsigned)j < (unsigned)nv) ? to_f32(img[j * nu + i]) : 0.f;
 }
 
-template <typename T>
+// Footprint of a voxel block on view v: the projective image of the index box
+// lies in the convex hull of its 8 projected corners, so [floor(min)-1,
+// floor(max)+2] in each detector direction covers every bilinear tap (with a
+// pixel of margin for rounding).  Computed by lanes 0..7 of every wave and
+// combined with shuffles, so each wave knows the box without a barrier.
+struct Box {
+  int i_lo, j_lo, w, h;
+};
+
+__device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int bx0, int bx1, int by0, int by1,
+                                               int bz0, int bz1) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 7;
+  const double x = (c & 1) ? bx1 : bx0, y = (c & 2) ? by1 : by0, z = (c & 4) ? bz1 : bz0;
+  const double den = fma(x, P[0], fma(y, P[1], fma(z, P[2], P[3])));
+  const double nu = fma(x, P[4], fma(y, P[5], fma(z, P[6], P[7])));
+  const double nv = fma(x, P[8], fma(y, P[9], fma(z, P[10], P[11])));
+  float iu = (float)(nu / den), jv = (float)(nv / den);
+  float imin = iu, imax = iu, jmin = jv, jmax = jv;
+#pragma unroll
+  for (int m = 1; m < 8; m <<= 1) {
+    imin = fminf(imin, __shfl_xor(imin, m, 8));
+    imax = fmaxf(imax, __shfl_xor(imax, m, 8));
+    jmin = fminf(jmin, __shfl_xor(jmin, m, 8));
+    jmax = fmaxf(jmax, __shfl_xor(jmax, m, 8));
+  }
+  imin = fmaxf(__shfl(imin, 0), -1.0e6f);
+  imax = fminf(__shfl(imax, 0), 1.0e6f);
+  jmin = fmaxf(__shfl(jmin, 0), -1.0e6f);
+  jmax = fminf(__shfl(jmax, 0), 1.0e6f);
+  Box b;
+  b.i_lo = (int)floorf(imin) - 1;
+  b.j_lo = (int)floorf(jmin) - 1;
+  b.w = (int)floorf(imax) + 3 - b.i_lo;
+  b.h = (int)floorf(jmax) + 3 - b.j_lo;
+  return b;
+}
+
+// STAGE = staged pixels per thread and view (the plan picks the smallest that
+// holds the largest footprint); STAGE == 0 selects direct global taps.
+template <typename T, int STAGE>
 __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
                                                  int nv) {
-  const int ix = blockIdx.x * kBX + threadIdx.x;
-  const int iy = blockIdx.y * kBY + threadIdx.y;
-  const int iz0 = blockIdx.z * kZC;
+  constexpr int kTile = STAGE > 0 ? 256 * STAGE : 1;
+  __shared__ float tile[2][kTile];
+  const int tid = threadIdx.y * kBX + threadIdx.x;
+  const int bx0 = blockIdx.x * kBX, by0 = blockIdx.y * kBY, bz0 = blockIdx.z * kZC;
+  const int bx1 = min(g.nx, bx0 + kBX) - 1, by1 = min(g.ny, by0 + kBY) - 1, bz1 = min(g.nz, bz0 + kZC) - 1;
+  const int ix = bx0 + threadIdx.x, iy = by0 + threadIdx.y, iz0 = bz0;
   float acc[kZC];
 #pragma unroll
   for (int z = 0; z < kZC; ++z) acc[z] = 0.f;
   const size_t npix = (size_t)g.nu * g.nv;
-  for (int v = v0; v < v0 + nv; ++v) {
-    const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
-    const T* img = gF + (size_t)v * npix;
+  if constexpr (STAGE == 0) {
+    for (int v = v0; v < v0 + nv; ++v) {
+      const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
+      const T* img = gF + (size_t)v * npix;
 #pragma unroll
-    for (int z = 0; z < kZC; ++z) {
-      const float den = fmaf((float)z, c.dden, c.den);
-      const float r = __builtin_amdgcn_rcpf(den);
-      const float u = fmaf((float)z, c.ldu, c.lu) * r;
-      const float w = fmaf((float)z, c.ldv, c.lv) * r;
-      const float fu0 = floorf(u), fw0 = floorf(w);
-      const float fu = u - fu0, fw = w - fw0;
-      const int i = c.iu0 + (int)fu0, j = c.jv0 + (int)fw0;
-      const float a00 = tap(img, i, j, g.nu, g.nv), a01 = tap(img, i + 1, j, g.nu, g.nv);
-      const float a10 = tap(img, i, j + 1, g.nu, g.nv), a11 = tap(img, i + 1, j + 1, g.nu, g.nv);
-      const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
-      acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
+      for (int z = 0; z < kZC; ++z) {
+        const float den = fmaf((float)z, c.dden, c.den);
+        const float r = __builtin_amdgcn_rcpf(den);
+        const float u = fmaf((float)z, c.ldu, c.lu) * r;
+        const float w = fmaf((float)z, c.ldv, c.lv) * r;
+        const float fu0 = floorf(u), fw0 = floorf(w);
+        const float fu = u - fu0, fw = w - fw0;
+        const int i = c.iu0 + (int)fu0, j = c.jv0 + (int)fw0;
+        const float a00 = tap(img, i, j, g.nu, g.nv), a01 = tap(img, i + 1, j, g.nu, g.nv);
+        const float a10 = tap(img, i, j + 1, g.nu, g.nv), a11 = tap(img, i + 1, j + 1, g.nu, g.nv);
+        const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
+        acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
+      }
+    }
+  } else {
+    float stg[STAGE > 0 ? STAGE : 1];
+    // fetch view v's footprint into registers (zero outside the detector)
+    auto load_stage = [&](int v, const Box& b) {
+      const T* img = gF + (size_t)v * npix;
+      const float invw = 1.0f / (float)b.w;
+#pragma unroll
+      for (int s = 0; s < STAGE; ++s) {
+        const int e = tid + 256 * s;
+        float val = 0.f;
+        if (e < b.w * b.h) {
+          const int row = (int)(((float)e + 0.5f) * invw);
+          const int col = e - row * b.w;
+          const int ii = b.i_lo + col, jj = b.j_lo + row;
+          if ((unsigned)ii < (unsigned)g.nu && (unsigned)jj < (unsigned)g.nv) val = to_f32(img[jj * g.nu + ii]);
+        }
+        stg[s] = val;
+      }
+    };
+    auto store_stage = [&](int buf, const Box& b) {
+#pragma unroll
+      for (int s = 0; s < STAGE; ++s) {
+        const int e = tid + 256 * s;
+        if (e < b.w * b.h) tile[buf][e] = stg[s];
+      }
+    };
+    Box cur{0, 0, 0, 0};
+    if (nv > 0) {
+      cur = block_footprint(proj + 12 * v0, bx0, bx1, by0, by1, bz0, bz1);
+      load_stage(v0, cur);
+      store_stage(0, cur);
+    }
+    __syncthreads();
+    for (int v = v0; v < v0 + nv; ++v) {
+      const int buf = (v - v0) & 1;
+      Box nxt{0, 0, 0, 0};
+      const bool more = v + 1 < v0 + nv;
+      if (more) {
+        nxt = block_footprint(proj + 12 * (v + 1), bx0, bx1, by0, by1, bz0, bz1);
+        load_stage(v + 1, nxt);
+      }
+      const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
+      const float* t = tile[buf];
+      const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
+      const int wm = cur.w - 2, hm = cur.h - 2;
+#pragma unroll
+      for (int z = 0; z < kZC; ++z) {
+        const float den = fmaf((float)z, c.dden, c.den);
+        const float r = __builtin_amdgcn_rcpf(den);
+        const float u = fmaf((float)z, c.ldu, c.lu) * r;
+        const float w = fmaf((float)z, c.ldv, c.lv) * r;
+        const float fu0 = floorf(u), fw0 = floorf(w);
+        const float fu = u - fu0, fw = w - fw0;
+        const int i = min(max(oi + (int)fu0, 0), wm), j = min(max(oj + (int)fw0, 0), hm);
+        const int q = j * cur.w + i;
+        const float a00 = t[q], a01 = t[q + 1], a10 = t[q + cur.w], a11 = t[q + cur.w + 1];
+        const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
+        acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
+        // keep the scheduler from hoisting every voxel's LDS reads at once
+        // (register pressure would cut occupancy to 2 waves per SIMD)
+        if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+      if (more) store_stage(buf ^ 1, nxt);
+      __syncthreads();
+      cur = nxt;
     }
   }
   if (ix >= g.nx || iy >= g.ny) return;
@@ -328,11 +443,21 @@ hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, 
   dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + kBY - 1) / kBY, (p.kg.nz + kZC - 1) / kZC);
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
-    hipLaunchKernelGGL((k_cone_bp<T>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, relu, v0,
-                       nv);
+#define DC_BP(ST) \
+  hipLaunchKernelGGL((k_cone_bp<T, ST>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, relu, v0, nv)
+    switch (p.bp_stage) {
+      case 4: DC_BP(4); break;
+      case 8: DC_BP(8); break;
+      case 12: DC_BP(12); break;
+      case 16: DC_BP(16); break;
+      default: DC_BP(0); break;
+    }
+#undef DC_BP
     return hipGetLastError();
   });
 }
+
+int cone_bp_block(int axis) { return axis == 0 ? kBX : axis == 1 ? kBY : kZC; }
 
 hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, void* GgF, dc_dtype tF, int v0,
                           int nv, hipStream_t s) {

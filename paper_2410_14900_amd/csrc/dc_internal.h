@@ -5,7 +5,7 @@
 #include <stdint.h>
 #include <string>
 
-#include "../../include/dcfbp.h"
+#include "dcfbp.h"
 
 namespace dc {
 
@@ -65,6 +65,7 @@ struct Plan {
   double* d_proj = nullptr;      // [V][12]
   float* d_rmax2 = nullptr;      // [V] upper bound of (D/U)^2 over the volume
   int cone_max_terms = 0;        // max voxels sharing one (pixel cell) index in one view
+  int bp_stage = 0;              // staged pixels per thread in the backprojection (0: global taps)
   // splat (Radon) work list: angle chunks that stay on one side of the diagonal
   int4* d_chunks = nullptr;      // (k0, count, column_major, 0)
   // plan-owned scratch: [0, V) per-view max |input| of the splat, [V] max |Gf| of
@@ -79,6 +80,9 @@ struct Plan {
 };
 
 void set_error(const std::string& msg);
+
+// backprojection voxel block edge along axis 0/1/2 (cone.hip)
+int cone_bp_block(int axis);
 
 // scratch helpers (radon2d.hip)
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
