@@ -99,7 +99,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
   // Radon work list: runs of angles whose pixels spread fastest along rows
   // (|A| >= |B|, lanes walk i) or along columns (lanes walk j), cut into chunks.
   // LDS holds kc rows of (n_s + 1) 64-bit accumulators (<= 64 KiB)
-  const int kc = std::max(1, std::min(16, 8192 / (g->n_s + 1)));
+  const int kc = std::max(1, std::min(8, 8192 / (g->n_s + 1)));
   p->splat_kc = kc;
   // bound on pixels sharing one bin on one angle, and whether every pixel's
   // bin index stays in [-1, n_s - 1] (then the splat needs no range checks)

@@ -26,8 +26,8 @@ namespace dc {
 // that no bin's a-sum can leave 32 bits (at most `max_terms` pixels share a bin
 // on one angle).
 //
-// The fractional bin t reaches ~n_s, where a float32 ulp is 1e-4 bin, so t is
-// formed in float64 (full-rate FMA on CDNA) and only the fraction is rounded.
+// The fractional bin t reaches ~n_s, where a float32 ulp is 1e-4 bin; it is kept
+// in exact 32.32 fixed point instead (see the walk below).
 __global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) p[q] = 0u;
 }
@@ -65,6 +65,8 @@ __global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img
   if (threadIdx.x == 0) atomicMax(vmax + v, __float_as_uint(red[0]));
 }
 
+static constexpr int kSplatKC = 8;   // max angles per workgroup (registers hold one t per angle)
+
 template <typename Tin, typename Tout, bool WCOS, bool CHECKED>
 __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout* __restrict__ out, KGrid g,
                                                const int4* __restrict__ chunks,
@@ -73,6 +75,7 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
                                                int max_terms, const unsigned* __restrict__ vmax_bits) {
   extern __shared__ unsigned long long acc[];   // [kn][n_s + 1], index m + 1
   __shared__ double sA[16], sB[16], sC[16];
+  __shared__ long long sStep[16];
   const int4 ch = chunks[blockIdx.x];
   const int v = v0 + blockIdx.y;
   const int k0 = ch.x, kn = ch.y, colmajor = ch.z;
@@ -86,38 +89,55 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
     sA[threadIdx.x] = angd[3 * k];
     sB[threadIdx.x] = angd[3 * k + 1];
     sC[threadIdx.x] = angd[3 * k + 2];
+    // step of t along the walk direction in 32.32 fixed point
+    sStep[threadIdx.x] = (long long)llrint((colmajor ? angd[3 * k] : angd[3 * k + 1]) * 4294967296.0);
   }
   __syncthreads();
   const float vmax = __uint_as_float(vmax_bits[v]);
   // quantum: |a| per bin stays below 2^31 - 1 with max_terms contributions
   const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
   const float S = vmax > 0.f ? qmax / vmax : 0.f;
-  for (int q = threadIdx.x; q < npix; q += blockDim.x) {
-    int i, j;
-    if (colmajor) {
-      i = q / g.nv;
-      j = q - i * g.nv;
-    } else {
-      j = q / g.nu;
-      i = q - j * g.nu;
+  // Threads own whole lines of pixels (columns when the angles spread rows,
+  // rows otherwise) and walk them; t advances by an exact fixed-point step, so
+  // the bin index is the high word and the fraction the low word, with a
+  // rounding drift below 2^-33 bin per step.
+  const int n_lines = colmajor ? g.nv : g.nu;
+  const int n_steps = colmajor ? g.nu : g.nv;
+  for (int line = threadIdx.x; line < n_lines; line += blockDim.x) {
+    long long t[kSplatKC];
+#pragma unroll
+    for (int kk = 0; kk < kSplatKC; ++kk) {
+      if (kk < kn) {
+        const double t0 = colmajor ? fma((double)line, sB[kk], sC[kk]) : fma((double)line, sA[kk], sC[kk]);
+        const double fl = floor(t0);
+        t[kk] = ((long long)(int)fl << 32) + (long long)(unsigned)((t0 - fl) * 4294967296.0);
+      } else {
+        t[kk] = 0;
+      }
     }
-    float x = to_f32(im[j * g.nu + i]);
-    if (WCOS) {
-      const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-      x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
-    }
-    const float xs = x * S;
-    const int qa = (int)rintf(xs);
-    const unsigned sa = (unsigned)(qa >> 31);        // sign extension of qa into the high word
-    const double di = (double)i, dj = (double)j;
-    for (int kk = 0; kk < kn; ++kk) {
-      const double t = fma(di, sA[kk], fma(dj, sB[kk], sC[kk]));
-      const double fl = floor(t);
-      const int m = (int)fl;
-      const int qb = (int)rintf(xs * (float)(t - fl));
-      const unsigned long long word =
-          ((unsigned long long)((unsigned)qb + sa) << 32) | (unsigned long long)(unsigned)qa;
-      if (!CHECKED || (unsigned)(m + 1) <= (unsigned)ns) atomicAdd(acc + kk * row + m + 1, word);
+    for (int p = 0; p < n_steps; ++p) {
+      const int i = colmajor ? p : line, j = colmajor ? line : p;
+      float x = to_f32(im[j * g.nu + i]);
+      if (WCOS) {
+        const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
+        x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+      }
+      const float xs = x * S;
+      const int qa = (int)rintf(xs);
+      const unsigned sa = (unsigned)(qa >> 31);        // sign extension of qa into the high word
+      const float xs2 = xs * 2.3283064365386963e-10f;  // xs * 2^-32
+#pragma unroll
+      for (int kk = 0; kk < kSplatKC; ++kk) {
+        if (kk < kn) {
+          const int m = (int)(t[kk] >> 32);
+          const unsigned lo = (unsigned)t[kk];
+          const int qb = (int)rintf(xs2 * (float)lo);
+          const unsigned long long word =
+              ((unsigned long long)((unsigned)qb + sa) << 32) | (unsigned long long)(unsigned)qa;
+          if (!CHECKED || (unsigned)(m + 1) <= (unsigned)ns) atomicAdd(acc + kk * row + m + 1, word);
+          t[kk] += sStep[kk];
+        }
+      }
     }
   }
   __syncthreads();
