@@ -27,13 +27,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel-view updates/s (fwd+bwd DC-FBP) at 256³; % HBM roofline; BF16 vs FP32"
 HBM_PEAK_GBS = 8000.0
-# float32 vector peak for non-packed FMA: 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
-FP32_PEAK_TFLOPS = 78.6
-FP32_PEAK_PUBLISHED = 157.3
+# float32 vector peak: 256 CU x 4 SIMD x 32 lanes/clk x 2 flops (FMA) x 2.4 GHz = 157.3 TFLOP/s;
+# gfx950 issues a wave64 float32 VALU op in 2 cycles without packed math (measured)
+FP32_PEAK_TFLOPS = 157.3
 
-# algorithmic work per unit (flops) of each stage, see the design doc
-FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 8, "cone_bp": 25,
-                  "cone_bp_adjoint": 25, "detector_bp_adjoint": 9, "filter_adjoint": 10}
+# algorithmic work per unit (flops) of each stage: pixel-angle pairs for the 2D
+# stages, voxel-view pairs for the cone stages, sinogram bins for the filter
+FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 9, "cone_bp": 23,
+                  "cone_bp_adjoint": 23, "detector_bp_adjoint": 9, "filter_adjoint": 10}
 
 
 def log(*a):
@@ -50,8 +51,8 @@ def stage_work(g, V, bpe_store):
         "filter": (V * nbin, V * nbin * (4 + 4 + bpe_store)),
         "detector_bp": (pa, V * nbin * bpe_store + V * npix * bpe_store),
         "cone_bp": (vv, V * npix * bpe_store + nvox * 4),
-        "cone_bp_adjoint": (vv, nvox * 4 * 2 + V * npix * 4),
-        "detector_bp_adjoint": (pa, V * npix * 4 + V * nbin * bpe_store),
+        "cone_bp_adjoint": (vv, nvox * 4 * 2 + V * npix * bpe_store),
+        "detector_bp_adjoint": (pa, V * npix * bpe_store + V * nbin * bpe_store),
         "filter_adjoint": (V * nbin, V * nbin * (bpe_store + 4 + 4)),
     }
 
@@ -87,7 +88,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", choices=["f32", "bf16", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=1)
+    ap.add_argument("--cpu-views", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path is single-GPU (views would shard across GPUs "
@@ -128,7 +129,7 @@ def main():
         H = torch.empty((V, K, S), device="cuda", dtype=sdt)
         gF = torch.empty((V, grid.nv, grid.nu), device="cuda", dtype=sdt)
         f = torch.empty((grid.nz, grid.ny, grid.nx), device="cuda")
-        GgF = torch.empty((V, grid.nv, grid.nu), device="cuda")
+        GgF = torch.empty((V, grid.nv, grid.nu), device="cuda", dtype=sdt)
         GH = torch.empty((V, K, S), device="cuda", dtype=sdt)
         M = torch.full((V, K, S), 0.5, device="cuda", requires_grad=True)
         GM = torch.empty((V, K, S), device="cuda")
@@ -183,7 +184,8 @@ def main():
             units, byts = work[s]
             t = kern[s] * 1e-3
             per_kernel[s] = {"ms": round(kern[s], 3), "GB/s": round(byts / t / 1e9, 1),
-                             "TFLOP/s": round(units * FLOPS_PER_UNIT[s] / t / 1e12, 2)}
+                             "TFLOP/s": round(units * FLOPS_PER_UNIT[s] / t / 1e12, 2),
+                             "units_per_s": units / t}
         results[store] = dict(ms=ms, kern=kern, per_kernel=per_kernel, work=work,
                               loss=float(loss_box["loss"]))
         del R, H, gF, f, GgF, GH, M, GM, opt
@@ -200,9 +202,8 @@ def main():
     else:
         ach = units * FLOPS_PER_UNIT[dom] / t / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
-                "peak_published_packed": FP32_PEAK_PUBLISHED, "unit": "TFLOP/s",
-                "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
-                "hbm_GBps": round(byts / t / 1e9, 1)}
+                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "hbm_GBps": round(byts / t / 1e9, 1), "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 5)}
     out = {
         "metric": METRIC,
         "value": nvox * V / (r["ms"] * 1e-3),

@@ -45,7 +45,7 @@ class _DCFBP(torch.autograd.Function):
         dev = M.device
         if R is None:
             R = sinogram(plan, g)
-        GgF = torch.empty((V,) + plan.det_shape, device=dev, dtype=torch.float32)
+        GgF = torch.empty((V,) + plan.det_shape, device=dev, dtype=ctx.store_dtype)
         ops.dc_cone_bp_adjoint(plan, Gf.contiguous(), GgF, f_relu=f)
         GH = torch.empty((V,) + plan.sino_shape, device=dev, dtype=ctx.store_dtype)
         ops.dc_detector_bp_adjoint(plan, GgF, GH)

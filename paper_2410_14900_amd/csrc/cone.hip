@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 // touches it, i.e. i* in [i0-1, i1), j* in [j0-1, j1).  In voxel-index space these
 // are four half-spaces L_k(x) >= 0 (affine because the projection is
 // projective with a positive denominator).  The voxels are enumerated as
-// x-runs of 8-voxel z-segments: every (z-segment, y) row of the volume is
+// x-runs of 16-voxel z-segments: every (z-segment, y) row of the volume is
 // intersected with the four half-spaces (a conservative x-interval; the exact
 // test is made per voxel), the non-empty rows are compacted into an LDS list,
 // and a flattened index over the list gives every lane one (x, y, z-segment)
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 // from max |Gf| (a reduction kernel into the plan's scratch) and the per-view
 // bound on (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
 // box can reach the tile's window are scanned.
-static constexpr int kFTI = 16, kFTJ = 64, kFZS = 8, kFROWS = 1024;
+static constexpr int kFTI = 16, kFTJ = 64, kFZS = 16, kFROWS = 1024;
 static constexpr int kFW = kFTI + 1, kFH = kFTJ + 1;
 
 __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf
   if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
 }
 
-static constexpr int kFMaxLayers = 128;
+static constexpr int kFMaxLayers = 64;
 
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, const float* __restrict__ f_relu,
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
     sCE[q] = 0ull;
   }
   __syncthreads();
-  // z-layers (8 slices each) whose box can reach the window under all four planes
+  // z-layers (16 slices each) whose box can reach the window under all four planes
   const int nzs = (g.nz + kFZS - 1) / kFZS;
   for (int zs = threadIdx.x; zs < nzs; zs += blockDim.x) {
     const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
   }
   __syncthreads();
   const int nrows = sNL * g.ny;
-  const size_t plane = (size_t)g.nx * g.ny;
+  const int plane = g.nx * g.ny;   // volumes are below 2^31 voxels (checked by the plan)
   const float gmax = __uint_as_float(*gmax_bits) * rmax2[v];
   const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
   const float S = gmax > 0.f ? qmax / gmax : 0.f;
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
     if (threadIdx.x == 255) sPre[cnt] = run;   // total (thread 255 holds the last entries)
     __syncthreads();
     const int total = sPre[cnt];
-    // 3. flattened items: (row, x) -> an 8-voxel z-segment
+    // 3. flattened items: (row, x) -> a 16-voxel z-segment
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
       int lo = 0, hi = cnt - 1;
       while (lo < hi) {                       // last row with sPre[row] <= q
@@ -386,31 +386,44 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
       const int zs = r / g.ny, iy = r - zs * g.ny;
       const int iz0 = zs * kFZS;
       const int nzv = min(kFZS, g.nz - iz0);
-      const size_t base = (size_t)iz0 * plane + (size_t)iy * g.nx + ix;
+      // Issue all of the segment's loads before using any of them (branch-free:
+      // indices past the volume are clamped into it and their values dropped),
+      // so their latencies overlap instead of serialising.
+      const int off = iz0 * plane + iy * g.nx + ix;
+      float gv[kFZS], mk[kFZS];
+#pragma unroll
+      for (int z = 0; z < kFZS; ++z) gv[z] = Gf[off + min(z, nzv - 1) * plane];
+      if (f_relu) {
+#pragma unroll
+        for (int z = 0; z < kFZS; ++z) mk[z] = f_relu[off + min(z, nzv - 1) * plane];
+      } else {
+#pragma unroll
+        for (int z = 0; z < kFZS; ++z) mk[z] = 1.f;
+      }
+#pragma unroll
+      for (int z = 0; z < kFZS; ++z) gv[z] = (z < nzv && mk[z] > 0.f) ? gv[z] : 0.f;
       const ColumnMap c = column_map(P, ix, iy, iz0);
-      for (int z = 0; z < nzv; ++z) {
+#pragma unroll
+      for (int z = 0; z < kFZS; ++z) {
         const float den = fmaf((float)z, c.dden, c.den);
         const float rr = __builtin_amdgcn_rcpf(den);
         const float u = fmaf((float)z, c.ldu, c.lu) * rr;
         const float w = fmaf((float)z, c.ldv, c.lv) * rr;
         const float fu0 = floorf(u), fw0 = floorf(w);
         const int li = c.iu0 + (int)fu0 - (i0 - 1), lj = c.jv0 + (int)fw0 - (j0 - 1);
-        if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0)) {
-          float x = Gf[base + z * plane];
-          if (f_relu && !(f_relu[base + z * plane] > 0.f)) x = 0.f;
-          if (x != 0.f) {
-            const float fu = u - fu0, fv = w - fw0;
-            const float gs = x * rr * rr * S;
-            const float gu = gs * fu;
-            const int qa = (int)rintf(gs), qb = (int)rintf(gu);
-            const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
-            const unsigned long long w1 =
-                ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
-            const unsigned long long w2 =
-                ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
-            atomicAdd(sAB + lj * kFW + li, w1);
-            atomicAdd(sCE + lj * kFW + li, w2);
-          }
+        const float x = gv[z];
+        if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
+          const float fu = u - fu0, fv = w - fw0;
+          const float gs = x * rr * rr * S;
+          const float gu = gs * fu;
+          const int qa = (int)rintf(gs), qb = (int)rintf(gu);
+          const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
+          const unsigned long long w1 =
+              ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
+          const unsigned long long w2 =
+              ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
+          atomicAdd(sAB + lj * kFW + li, w1);
+          atomicAdd(sCE + lj * kFW + li, w2);
         }
       }
     }
