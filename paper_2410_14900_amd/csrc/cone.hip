@@ -208,8 +208,9 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 
 // ------------------------------------------------------------- transpose
 // Gather form of the transpose, without global atomics: one workgroup owns one
-// 16 x 64 pixel tile of one view and visits every voxel whose bilinear footprint
-// touches it, i.e. i* in [i0-1, i1), j* in [j0-1, j1).  In voxel-index space these
+// 16 x 64 pixel tile of 2 consecutive views and visits every voxel whose bilinear
+// footprint touches it on any of them (each voxel segment is loaded once and
+// projected on every view), i.e. i* in [i0-1, i1), j* in [j0-1, j1).  In voxel-index space these
 // are four half-spaces L_k(x) >= 0 (affine because the projection is
 // projective with a positive denominator).  The voxels are enumerated as
 // x-runs of 16-voxel z-segments: every (z-segment, y) row of the volume is
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 // from max |Gf| (a reduction kernel into the plan's scratch) and the per-view
 // bound on (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
 // box can reach the tile's window are scanned.
-static constexpr int kFTI = 16, kFTJ = 64, kFZS = 16, kFROWS = 1024;
+static constexpr int kFTI = 16, kFTJ = 64, kFZS = 16, kFROWS = 512;
 static constexpr int kFW = kFTI + 1, kFH = kFTJ + 1;
 
 __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
@@ -268,51 +269,61 @@ __global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf
 
 static constexpr int kFMaxLayers = 64;
 
+static constexpr int kFV = 2;   // consecutive views per workgroup (their frusta nearly coincide)
+
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, const float* __restrict__ f_relu,
                                                  Tout* __restrict__ GgF, KGrid g, const double* __restrict__ proj,
-                                                 const float* __restrict__ rmax2, int v0, int tiles_u,
+                                                 const float* __restrict__ rmax2, int v0, int nv, int tiles_u,
                                                  int max_terms, const unsigned* __restrict__ gmax_bits) {
-  __shared__ double sL[4][4], sNegInvA[4];
+  __shared__ double sL[kFV][4][4], sNegInvA[kFV][4];
   __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
   __shared__ int sScan[256];
   __shared__ int sCount, sNL;
   __shared__ unsigned char sLayerOn[kFMaxLayers];
   __shared__ int sLayer[kFMaxLayers];
-  __shared__ unsigned long long sAB[kFW * kFH], sCE[kFW * kFH];
-  const int v = v0 + blockIdx.y;
+  __shared__ unsigned long long sAB[kFV][kFW * kFH], sCE[kFV][kFW * kFH];
+  const int va = v0 + blockIdx.y * kFV;
+  const int nvw = min(kFV, v0 + nv - va);
   const int ti = blockIdx.x % tiles_u, tj = blockIdx.x / tiles_u;
   const int i0 = ti * kFTI, i1 = min(g.nu, i0 + kFTI);
   const int j0 = tj * kFTJ, j1 = min(g.nv, j0 + kFTJ);
-  const double* P = proj + 12 * v;
-  if (threadIdx.x < 16) {
-    const int k = threadIdx.x >> 2, c = threadIdx.x & 3;
-    const double den = P[c], nu = P[4 + c], nvv = P[8 + c];
-    double val;
-    if (k == 0) val = nu - (i0 - 1) * den;        // i* >= i0 - 1
-    else if (k == 1) val = i1 * den - nu;         // i* <  i1
-    else if (k == 2) val = nvv - (j0 - 1) * den;  // j* >= j0 - 1
-    else val = j1 * den - nvv;                    // j* <  j1
-    sL[k][c] = val;
-    if (c == 0) sNegInvA[k] = val != 0.0 ? -1.0 / val : 0.0;
+  if (threadIdx.x < 16 * kFV) {
+    const int w = threadIdx.x >> 4, k = (threadIdx.x >> 2) & 3, c = threadIdx.x & 3;
+    if (w < nvw) {
+      const double* P = proj + 12 * (va + w);
+      const double den = P[c], nu = P[4 + c], nvv = P[8 + c];
+      double val;
+      if (k == 0) val = nu - (i0 - 1) * den;        // i* >= i0 - 1
+      else if (k == 1) val = i1 * den - nu;         // i* <  i1
+      else if (k == 2) val = nvv - (j0 - 1) * den;  // j* >= j0 - 1
+      else val = j1 * den - nvv;                    // j* <  j1
+      sL[w][k][c] = val;
+      if (c == 0) sNegInvA[w][k] = val != 0.0 ? -1.0 / val : 0.0;
+    }
   }
-  for (int q = threadIdx.x; q < kFW * kFH; q += blockDim.x) {
-    sAB[q] = 0ull;
-    sCE[q] = 0ull;
+  for (int q = threadIdx.x; q < kFV * kFW * kFH; q += blockDim.x) {
+    (&sAB[0][0])[q] = 0ull;
+    (&sCE[0][0])[q] = 0ull;
   }
   __syncthreads();
-  // z-layers (16 slices each) whose box can reach the window under all four planes
+  // z-layers (16 slices each) whose box can reach the window of any of the views
   const int nzs = (g.nz + kFZS - 1) / kFZS;
   for (int zs = threadIdx.x; zs < nzs; zs += blockDim.x) {
     const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
-    bool on = true;
+    bool any = false;
+    for (int w = 0; w < nvw; ++w) {
+      bool on = true;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double mxl = fmax(sL[k][0] * 0.0, sL[k][0] * (g.nx - 1)) + fmax(sL[k][1] * 0.0, sL[k][1] * (g.ny - 1)) +
-                         fmax(sL[k][2] * zlo, sL[k][2] * zhi) + sL[k][3];
-      if (mxl < -1e-6 * fabs(sL[k][3]) - 1e-6) on = false;
+      for (int k = 0; k < 4; ++k) {
+        const double* L = sL[w][k];
+        const double mxl = fmax(0.0, L[0] * (g.nx - 1)) + fmax(0.0, L[1] * (g.ny - 1)) +
+                           fmax(L[2] * zlo, L[2] * zhi) + L[3];
+        if (mxl < -1e-6 * fabs(L[3]) - 1e-6) on = false;
+      }
+      any = any || on;
     }
-    sLayerOn[zs] = on;
+    sLayerOn[zs] = any;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -324,34 +335,47 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
   __syncthreads();
   const int nrows = sNL * g.ny;
   const int plane = g.nx * g.ny;   // volumes are below 2^31 voxels (checked by the plan)
-  const float gmax = __uint_as_float(*gmax_bits) * rmax2[v];
   const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
-  const float S = gmax > 0.f ? qmax / gmax : 0.f;
+  const float gabs = __uint_as_float(*gmax_bits);
+  float S[kFV];
+#pragma unroll
+  for (int w = 0; w < kFV; ++w) {
+    const float gmax = w < nvw ? gabs * rmax2[va + w] : 0.f;
+    S[w] = gmax > 0.f ? qmax / gmax : 0.f;
+  }
   for (int r0 = 0; r0 < nrows; r0 += kFROWS) {
     if (threadIdx.x == 0) sCount = 0;
     __syncthreads();
-    // 1. rows of this batch whose x-interval may meet the frustum
+    // 1. rows of this batch whose x-interval may meet one of the frusta
     for (int r = r0 + threadIdx.x; r < min(nrows, r0 + kFROWS); r += blockDim.x) {
       const int li = r / g.ny, iy = r - li * g.ny;
       const int zs = sLayer[li];
       const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
-      double xlo = 0.0, xhi = g.nx - 1;
-      bool empty = false;
+      double ulo = 1e30, uhi = -1e30;
+      for (int w = 0; w < nvw; ++w) {
+        double xlo = 0.0, xhi = g.nx - 1;
+        bool empty = false;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double a = sL[k][0];
-        const double c0 = fma(sL[k][1], (double)iy, sL[k][3]);
-        const double cm = fmax(fma(sL[k][2], zlo, c0), fma(sL[k][2], zhi, c0));
-        const double xb = cm * sNegInvA[k];      // L_k = a x + cm crosses zero here
-        if (a > 0.0) xlo = fmax(xlo, ceil(xb) - 1.0);
-        else if (a < 0.0) xhi = fmin(xhi, floor(xb) + 1.0);
-        else if (cm < 0.0) empty = true;
+        for (int k = 0; k < 4; ++k) {
+          const double* L = sL[w][k];
+          const double a = L[0];
+          const double c0 = fma(L[1], (double)iy, L[3]);
+          const double cm = fmax(fma(L[2], zlo, c0), fma(L[2], zhi, c0));
+          const double xb = cm * sNegInvA[w][k];      // L_k = a x + cm crosses zero here
+          if (a > 0.0) xlo = fmax(xlo, ceil(xb) - 1.0);
+          else if (a < 0.0) xhi = fmin(xhi, floor(xb) + 1.0);
+          else if (cm < 0.0) empty = true;
+        }
+        if (!empty && xlo <= xhi) {
+          ulo = fmin(ulo, xlo);
+          uhi = fmax(uhi, xhi);
+        }
       }
-      if (!empty && xlo <= xhi) {
+      if (ulo <= uhi) {
         const int slot = atomicAdd(&sCount, 1);
         sRow[slot] = zs * g.ny + iy;
-        sXlo[slot] = (int)xlo;
-        sPre[slot] = (int)(xhi - xlo) + 1;   // length for now
+        sXlo[slot] = (int)ulo;
+        sPre[slot] = (int)(uhi - ulo) + 1;   // length for now
       }
     }
     __syncthreads();
@@ -374,7 +398,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
     if (threadIdx.x == 255) sPre[cnt] = run;   // total (thread 255 holds the last entries)
     __syncthreads();
     const int total = sPre[cnt];
-    // 3. flattened items: (row, x) -> a 16-voxel z-segment
+    // 3. flattened items: (row, x) -> a 16-voxel z-segment, projected on every view
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
       int lo = 0, hi = cnt - 1;
       while (lo < hi) {                       // last row with sPre[row] <= q
@@ -402,52 +426,62 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
       }
 #pragma unroll
       for (int z = 0; z < kFZS; ++z) gv[z] = (z < nzv && mk[z] > 0.f) ? gv[z] : 0.f;
-      const ColumnMap c = column_map(P, ix, iy, iz0);
+      for (int w = 0; w < nvw; ++w) {
+        const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
+        const float Sw = S[0] * 0.f + (w == 0 ? S[0] : w == 1 ? S[1] : w == 2 ? S[2] : S[3]);
+        unsigned long long* ab = sAB[w];
+        unsigned long long* ce = sCE[w];
 #pragma unroll
-      for (int z = 0; z < kFZS; ++z) {
-        const float den = fmaf((float)z, c.dden, c.den);
-        const float rr = __builtin_amdgcn_rcpf(den);
-        const float u = fmaf((float)z, c.ldu, c.lu) * rr;
-        const float w = fmaf((float)z, c.ldv, c.lv) * rr;
-        const float fu0 = floorf(u), fw0 = floorf(w);
-        const int li = c.iu0 + (int)fu0 - (i0 - 1), lj = c.jv0 + (int)fw0 - (j0 - 1);
-        const float x = gv[z];
-        if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
-          const float fu = u - fu0, fv = w - fw0;
-          const float gs = x * rr * rr * S;
-          const float gu = gs * fu;
-          const int qa = (int)rintf(gs), qb = (int)rintf(gu);
-          const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
-          const unsigned long long w1 =
-              ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
-          const unsigned long long w2 =
-              ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
-          atomicAdd(sAB + lj * kFW + li, w1);
-          atomicAdd(sCE + lj * kFW + li, w2);
+        for (int z = 0; z < kFZS; ++z) {
+          const float den = fmaf((float)z, c.dden, c.den);
+          const float rr = __builtin_amdgcn_rcpf(den);
+          const float u = fmaf((float)z, c.ldu, c.lu) * rr;
+          const float wv = fmaf((float)z, c.ldv, c.lv) * rr;
+          const float fu0 = floorf(u), fw0 = floorf(wv);
+          const int li = c.iu0 + (int)fu0 - (i0 - 1), lj = c.jv0 + (int)fw0 - (j0 - 1);
+          const float x = gv[z];
+          if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
+            const float fu = u - fu0, fv = wv - fw0;
+            const float gs = x * rr * rr * Sw;
+            const float gu = gs * fu;
+            const int qa = (int)rintf(gs), qb = (int)rintf(gu);
+            const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
+            const unsigned long long w1 =
+                ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
+            const unsigned long long w2 =
+                ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
+            atomicAdd(ab + lj * kFW + li, w1);
+            atomicAdd(ce + lj * kFW + li, w2);
+          }
         }
       }
     }
     __syncthreads();
   }
-  // decode the tile
-  const double inv = S > 0.f ? 1.0 / (double)S : 0.0;
+  // decode the tiles
   auto lo32 = [](unsigned long long w) { return (long long)(int)(unsigned)(w & 0xffffffffull); };
   auto hi32 = [](unsigned long long w, long long lo) { return ((long long)w - lo) >> 32; };
-  Tout* o = GgF + (size_t)v * g.nu * g.nv;
-  for (int q = threadIdx.x; q < kFTI * kFTJ; q += blockDim.x) {
-    const int di = q % kFTI, dj = q / kFTI;
-    const int i = i0 + di, j = j0 + dj;
-    if (i >= i1 || j >= j1) continue;
-    const int li = di + 1, lj = dj + 1;
-    const unsigned long long ab = sAB[lj * kFW + li], ce = sCE[lj * kFW + li];
-    const unsigned long long abl = sAB[lj * kFW + li - 1], cel = sCE[lj * kFW + li - 1];
-    const unsigned long long ced = sCE[(lj - 1) * kFW + li], celd = sCE[(lj - 1) * kFW + li - 1];
-    const long long A = lo32(ab), B = hi32(ab, A), C = lo32(ce), E = hi32(ce, C);
-    const long long Bl = hi32(abl, lo32(abl)), Cl = lo32(cel), El = hi32(cel, Cl);
-    const long long Cd = lo32(ced), Ed = hi32(ced, Cd);
-    const long long Eld = hi32(celd, lo32(celd));
-    const long long val = A - B - C + E + (Bl - El) + (Cd - Ed) + Eld;
-    o[j * g.nu + i] = from_f32<Tout>((float)((double)val * inv));
+  for (int w = 0; w < nvw; ++w) {
+    const double inv = S[0] * 0.f + (w == 0 ? S[0] : w == 1 ? S[1] : w == 2 ? S[2] : S[3]);
+    const double invS = inv > 0.0 ? 1.0 / inv : 0.0;
+    const unsigned long long* AB = sAB[w];
+    const unsigned long long* CE = sCE[w];
+    Tout* o = GgF + (size_t)(va + w) * g.nu * g.nv;
+    for (int q = threadIdx.x; q < kFTI * kFTJ; q += blockDim.x) {
+      const int di = q % kFTI, dj = q / kFTI;
+      const int i = i0 + di, j = j0 + dj;
+      if (i >= i1 || j >= j1) continue;
+      const int li = di + 1, lj = dj + 1;
+      const unsigned long long ab = AB[lj * kFW + li], ce = CE[lj * kFW + li];
+      const unsigned long long abl = AB[lj * kFW + li - 1], cel = CE[lj * kFW + li - 1];
+      const unsigned long long ced = CE[(lj - 1) * kFW + li], celd = CE[(lj - 1) * kFW + li - 1];
+      const long long A = lo32(ab), B = hi32(ab, A), C = lo32(ce), E = hi32(ce, C);
+      const long long Bl = hi32(abl, lo32(abl)), Cl = lo32(cel), El = hi32(cel, Cl);
+      const long long Cd = lo32(ced), Ed = hi32(ced, Cd);
+      const long long Eld = hi32(celd, lo32(celd));
+      const long long val = A - B - C + E + (Bl - El) + (Cd - Ed) + Eld;
+      o[j * g.nu + i] = from_f32<Tout>((float)((double)val * invS));
+    }
   }
 }
 
@@ -482,11 +516,11 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
   const int blocks = (int)std::min<size_t>(2048, (n + 255) / 256);
   hipLaunchKernelGGL(k_vol_absmax, dim3(blocks), dim3(256), 0, s, Gf, f_relu, n, gmax);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  dim3 grid(tiles_u * tiles_v, nv);
+  dim3 grid(tiles_u * tiles_v, (nv + kFV - 1) / kFV);
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
     hipLaunchKernelGGL((k_cone_fp<T>), grid, dim3(256), 0, s, Gf, f_relu, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
-                       tiles_u, p.cone_max_terms, gmax);
+                       nv, tiles_u, p.cone_max_terms, gmax);
     return hipGetLastError();
   });
 }
