@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "bf16", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=4)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this path is single-GPU (views would shard across GPUs "
@@ -116,6 +118,15 @@ def main():
     del g64
     target = synth.voxelize_torch(ell, grid, device="cuda")
     plan = P.Plan(grid, views)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written" % (args.copy_calibration_mib, args.copy_calibration_mib))
+        del src, dst
     torch.cuda.synchronize()
     log("inputs ready")
 
@@ -166,7 +177,7 @@ def main():
         for _ in range(args.warmup):
             run(False)
         torch.cuda.synchronize()
-        log(store, "warmup done, loss", float(loss_box["loss"]))
+        log(store, "warmup done, loss", float(loss_box["loss"]) if loss_box else None)
         t0 = time.perf_counter()
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start.record(stream)

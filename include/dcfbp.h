@@ -39,10 +39,11 @@
  * dtype, alignment, view range); dc_last_error() gives a thread-local message.
  * A fault inside a kernel surfaces at the caller's next synchronisation.
  * Ownership: the caller owns every array; the plan owns its small device
- * tables (immutable after creation) and a scratch word per view that
+ * tables (immutable after creation), a scratch word per view that
  * dc_weight_radon, dc_detector_bp_adjoint and dc_cone_bp_adjoint use for their
- * fixed-point scales, so stage calls on one plan must be ordered on one stream
- * (use one plan per concurrent stream).  Plans must be created before any stream
+ * fixed-point scales, and one volume-sized float32 buffer into which
+ * dc_cone_bp_adjoint writes the ReLU-masked gradient; stage calls on one plan
+ * must therefore be ordered on one stream (use one plan per concurrent stream).  Plans must be created before any stream
  * capture that uses them; stage calls enqueue kernels only (no memset, no
  * allocation), so they can be captured into a graph.
  * Determinism: every stage returns bit-identical results for identical inputs

@@ -230,14 +230,16 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
       (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
       (e = up((void**)&p->d_rmax2, rmax2.data(), rmax2.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess ||
-      (e = hipMalloc((void**)&p->d_scratch, (n + 1) * sizeof(unsigned))) != hipSuccess)
+      (e = hipMalloc((void**)&p->d_scratch, (n + 1) * sizeof(unsigned))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_masked, (size_t)g->nx * g->ny * g->nz * sizeof(float))) != hipSuccess)
     return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP,
                 std::string("plan upload: ") + hipGetErrorString(e));
   return DC_OK;
 }
 
 static void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_ang, p->d_angf, p->d_trig, p->d_view, p->d_proj, p->d_rmax2, p->d_chunks, p->d_scratch};
+  void* ptrs[] = {p->d_ang,    p->d_angf,   p->d_trig,    p->d_view,  p->d_proj,
+                  p->d_rmax2,  p->d_chunks, p->d_scratch, p->d_masked};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;

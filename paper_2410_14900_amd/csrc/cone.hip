@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 
 // ------------------------------------------------------------- transpose
 // Gather form of the transpose, without global atomics: one workgroup owns one
-// 16 x 64 pixel tile of 2 consecutive views and visits every voxel whose bilinear
+// 8 x 64 pixel tile of 4 consecutive views and visits every voxel whose bilinear
 // footprint touches it on any of them (each voxel segment is loaded once and
 // projected on every view), i.e. i* in [i0-1, i1), j* in [j0-1, j1).  In voxel-index space these
 // are four half-spaces L_k(x) >= 0 (affine because the projection is
@@ -226,10 +226,11 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 // LDS integer atomics; the tile is decoded at the end as
 //   out(i,j) = A - B - C + E |(i,j) + (B - E)|(i-1,j) + (C - E)|(i,j-1) + E|(i-1,j-1).
 // Integer sums make the result bit-reproducible.  The fixed-point quantum comes
-// from max |Gf| (a reduction kernel into the plan's scratch) and the per-view
-// bound on (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
+// from max |Gf| (a reduction kernel into the plan's scratch, which also applies
+// the ReLU mask once into the plan's volume buffer) and the per-view bound on
+// (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
 // box can reach the tile's window are scanned.
-static constexpr int kFTI = 16, kFTJ = 64, kFZS = 16, kFROWS = 512;
+static constexpr int kFTI = 8, kFTJ = 64, kFZS = 16, kFROWS = 512;
 static constexpr int kFW = kFTI + 1, kFH = kFTJ + 1;
 
 __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
@@ -248,14 +249,19 @@ __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
   return incl - v;
 }
 
-// max |Gf * mask| over the volume, as float bits
+// max |Gf * mask| over the volume, as float bits; with a mask the masked
+// gradient is also written out (once) for the gather to read
 __global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf, const float* __restrict__ f_relu,
-                                                    size_t n, unsigned* __restrict__ out) {
+                                                    size_t n, unsigned* __restrict__ out,
+                                                    float* __restrict__ masked) {
   __shared__ float red[256];
   float mx = 0.f;
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
     float x = Gf[q];
-    if (f_relu && !(f_relu[q] > 0.f)) x = 0.f;
+    if (f_relu) {
+      x = f_relu[q] > 0.f ? x : 0.f;
+      masked[q] = x;
+    }
     mx = fmaxf(mx, fabsf(x));
   }
   red[threadIdx.x] = mx;
@@ -269,13 +275,12 @@ __global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf
 
 static constexpr int kFMaxLayers = 64;
 
-static constexpr int kFV = 2;   // consecutive views per workgroup (their frusta nearly coincide)
+static constexpr int kFV = 4;   // consecutive views per workgroup (their frusta nearly coincide)
 
 template <typename Tout>
-__global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, const float* __restrict__ f_relu,
-                                                 Tout* __restrict__ GgF, KGrid g, const double* __restrict__ proj,
+__global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g, const double* __restrict__ proj,
                                                  const float* __restrict__ rmax2, int v0, int nv, int tiles_u,
-                                                 int max_terms, const unsigned* __restrict__ gmax_bits) {
+                                                 int n_tiles, int max_terms, const unsigned* __restrict__ gmax_bits) {
   __shared__ double sL[kFV][4][4], sNegInvA[kFV][4];
   __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
   __shared__ int sScan[256];
@@ -283,9 +288,17 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
   __shared__ unsigned char sLayerOn[kFMaxLayers];
   __shared__ int sLayer[kFMaxLayers];
   __shared__ unsigned long long sAB[kFV][kFW * kFH], sCE[kFV][kFW * kFH];
-  const int va = v0 + blockIdx.y * kFV;
+  // XCD-aware order: workgroup b runs on XCD b % 8; each XCD takes every 8th
+  // tile and sweeps it through all view groups, so the ~100 workgroups resident
+  // on an XCD share one tile, whose voxels over all views (a thin annulus)
+  // stay in that XCD's L2.
+  const int ngroups = (nv + kFV - 1) / kFV;
+  const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int tile = xcd + 8 * (k / ngroups);
+  if (tile >= n_tiles) return;
+  const int va = v0 + (k % ngroups) * kFV;
   const int nvw = min(kFV, v0 + nv - va);
-  const int ti = blockIdx.x % tiles_u, tj = blockIdx.x / tiles_u;
+  const int ti = tile % tiles_u, tj = tile / tiles_u;
   const int i0 = ti * kFTI, i1 = min(g.nu, i0 + kFTI);
   const int j0 = tj * kFTJ, j1 = min(g.nv, j0 + kFTJ);
   if (threadIdx.x < 16 * kFV) {
@@ -414,18 +427,11 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, c
       // indices past the volume are clamped into it and their values dropped),
       // so their latencies overlap instead of serialising.
       const int off = iz0 * plane + iy * g.nx + ix;
-      float gv[kFZS], mk[kFZS];
+      float gv[kFZS];
 #pragma unroll
       for (int z = 0; z < kFZS; ++z) gv[z] = Gf[off + min(z, nzv - 1) * plane];
-      if (f_relu) {
 #pragma unroll
-        for (int z = 0; z < kFZS; ++z) mk[z] = f_relu[off + min(z, nzv - 1) * plane];
-      } else {
-#pragma unroll
-        for (int z = 0; z < kFZS; ++z) mk[z] = 1.f;
-      }
-#pragma unroll
-      for (int z = 0; z < kFZS; ++z) gv[z] = (z < nzv && mk[z] > 0.f) ? gv[z] : 0.f;
+      for (int z = 0; z < kFZS; ++z) gv[z] = z < nzv ? gv[z] : 0.f;
       for (int w = 0; w < nvw; ++w) {
         const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
         const float Sw = S[0] * 0.f + (w == 0 ? S[0] : w == 1 ? S[1] : w == 2 ? S[2] : S[3]);
@@ -514,13 +520,15 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
   if (e != hipSuccess) return e;
   const size_t n = (size_t)p.kg.nx * p.kg.ny * p.kg.nz;
   const int blocks = (int)std::min<size_t>(2048, (n + 255) / 256);
-  hipLaunchKernelGGL(k_vol_absmax, dim3(blocks), dim3(256), 0, s, Gf, f_relu, n, gmax);
+  hipLaunchKernelGGL(k_vol_absmax, dim3(blocks), dim3(256), 0, s, Gf, f_relu, n, gmax, p.d_masked);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  dim3 grid(tiles_u * tiles_v, (nv + kFV - 1) / kFV);
+  const int n_tiles = tiles_u * tiles_v, ngroups = (nv + kFV - 1) / kFV;
+  dim3 grid(8 * ((n_tiles + 7) / 8) * ngroups);
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
-    hipLaunchKernelGGL((k_cone_fp<T>), grid, dim3(256), 0, s, Gf, f_relu, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
-                       nv, tiles_u, p.cone_max_terms, gmax);
+    const float* src = f_relu ? p.d_masked : Gf;
+    hipLaunchKernelGGL((k_cone_fp<T>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, nv,
+                       tiles_u, n_tiles, p.cone_max_terms, gmax);
     return hipGetLastError();
   });
 }

@@ -72,6 +72,9 @@ struct Plan {
   // the cone adjoint (float bits, reduced with integer atomicMax).  Calls on one
   // plan must therefore be ordered on one stream.
   unsigned* d_scratch = nullptr; // [V + 1]
+  // volume-sized scratch for dc_cone_bp_adjoint with a ReLU mask: Gf * [f > 0]
+  // is formed once so the gather reads one array instead of two
+  float* d_masked = nullptr;     // [nz][ny][nx]
   int n_chunks = 0;
   int splat_kc = 0;              // max angles per chunk
   int splat_max_terms = 0;       // max pixels that share one (angle, bin)

@@ -71,13 +71,18 @@ template <typename Tin, typename Tout, bool WCOS, bool CHECKED>
 __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout* __restrict__ out, KGrid g,
                                                const int4* __restrict__ chunks,
                                                const double* __restrict__ angd,
-                                               const float4* __restrict__ viewf, float scale, int v0,
-                                               int max_terms, const unsigned* __restrict__ vmax_bits) {
+                                               const float4* __restrict__ viewf, float scale, int v0, int nv,
+                                               int n_chunks, int max_terms, const unsigned* __restrict__ vmax_bits) {
   extern __shared__ unsigned long long acc[];   // [kn][n_s + 1], index m + 1
   __shared__ double sA[16], sB[16], sC[16];
   __shared__ long long sStep[16];
-  const int4 ch = chunks[blockIdx.x];
-  const int v = v0 + blockIdx.y;
+  // XCD-aware order: workgroup b runs on XCD b % 8; all angle chunks of a view
+  // go to the same XCD, so the view's image is fetched from HBM into one L2.
+  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int vl = xcd + 8 * (kb / n_chunks);
+  if (vl >= nv) return;
+  const int4 ch = chunks[kb % n_chunks];
+  const int v = v0 + vl;
   const int k0 = ch.x, kn = ch.y, colmajor = ch.z;
   const int ns = g.n_s, row = ns + 1;
   const int npix = g.nu * g.nv;
@@ -169,13 +174,18 @@ template <typename Tin, typename Tout, bool WCOS>
 __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, Tout* __restrict__ out, KGrid g,
                                                 const double* __restrict__ angd,
                                                 const float4* __restrict__ angf,
-                                                const float4* __restrict__ viewf, float scale, int v0, int wl,
-                                                int tiles_u) {
+                                                const float4* __restrict__ viewf, float scale, int v0, int nv,
+                                                int wl, int tiles_u, int n_tiles) {
   extern __shared__ float2 win[];
   __shared__ float sOff[kKC], sA[kKC], sB[kKC];
   __shared__ int sW0[kKC];
-  const int v = v0 + blockIdx.y;
-  const int tu = blockIdx.x % tiles_u, tv = blockIdx.x / tiles_u;
+  // XCD-aware order: all tiles of a view run on one XCD (its sinogram stays in one L2)
+  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int vl = xcd + 8 * (kb / n_tiles);
+  if (vl >= nv) return;
+  const int v = v0 + vl;
+  const int tile = kb % n_tiles;
+  const int tu = tile % tiles_u, tv = tile / tiles_u;
   const int i0 = tu * kTX, j0 = tv * kTY;
   const int tx = threadIdx.x & (kTX - 1), ty = threadIdx.x / kTX;  // ty in [0, 8)
   const int ns = g.n_s;
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, To
 hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale, void* out,
                         dc_dtype t_out, int v0, int nv, hipStream_t s) {
   const size_t lds = (size_t)p.splat_kc * (p.kg.n_s + 1) * sizeof(unsigned long long);
-  dim3 grid(p.n_chunks, nv);
+  dim3 grid(8 * ((nv + 7) / 8) * p.n_chunks);
   hipError_t e = launch_zero_u32(p.d_scratch + v0, nv, s);
   if (e != hipSuccess) return e;
   return by_dtype(t_in, [&](auto tin) {
@@ -256,7 +266,8 @@ hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos
       using Tout = decltype(tout);
 #define DC_SPLAT(W, C)                                                                                         \
   hipLaunchKernelGGL((k_splat<Tin, Tout, W, C>), grid, dim3(512), lds, s, (const Tin*)img, (Tout*)out, p.kg,  \
-                     p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, p.splat_max_terms, p.d_scratch)
+                     p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, nv, p.n_chunks, p.splat_max_terms, \
+                     p.d_scratch)
       if (wcos) {
         if (p.splat_checked) DC_SPLAT(true, true); else DC_SPLAT(true, false);
       } else {
@@ -272,7 +283,8 @@ hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wc
                          dc_dtype t_out, int v0, int nv, hipStream_t s) {
   const int tiles_u = (p.kg.nu + kTX - 1) / kTX, tiles_v = (p.kg.nv + kTY - 1) / kTY;
   const size_t lds = (size_t)kKC * p.interp_wl * sizeof(float2);
-  dim3 grid(tiles_u * tiles_v, nv);
+  const int n_tiles = tiles_u * tiles_v;
+  dim3 grid(8 * ((nv + 7) / 8) * n_tiles);
   return by_dtype(t_in, [&](auto tin) {
     using Tin = decltype(tin);
     return by_dtype(t_out, [&](auto tout) {
@@ -280,11 +292,11 @@ hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wc
       if (wcos)
         hipLaunchKernelGGL((k_interp<Tin, Tout, true>), grid, dim3(256), lds, s, (const Tin*)rows, (Tout*)out,
                            p.kg, p.d_ang, (const float4*)p.d_angf, (const float4*)p.d_view, scale, v0,
-                           p.interp_wl, tiles_u);
+                           nv, p.interp_wl, tiles_u, n_tiles);
       else
         hipLaunchKernelGGL((k_interp<Tin, Tout, false>), grid, dim3(256), lds, s, (const Tin*)rows, (Tout*)out,
                            p.kg, p.d_ang, (const float4*)p.d_angf, (const float4*)p.d_view, scale, v0,
-                           p.interp_wl, tiles_u);
+                           nv, p.interp_wl, tiles_u, n_tiles);
       return hipGetLastError();
     });
   });
