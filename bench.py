@@ -16,6 +16,8 @@ times, the dominant kernel's roofline and the CPU oracle baseline.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -35,6 +37,28 @@ FP32_PEAK_TFLOPS = 157.3
 # stages, voxel-view pairs for the cone stages, sinogram bins for the filter
 FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 9, "cone_bp": 23,
                   "cone_bp_adjoint": 23, "detector_bp_adjoint": 9, "filter_adjoint": 10}
+
+
+# HBM bytes per call of a stage, from FETCH_SIZE and WRITE_SIZE counter runs of this
+# script (each scaled by what the counter reads for a 1 GiB copy; summaries in
+# profiles/c2_<dtype>_hbm_traffic.md).  A figure holds only for the kernel sources it
+# was measured on, identified by KERNEL_SOURCES_DIGEST; after any change to them the
+# roofline reports traffic as null until the counters are taken again.
+MEASURED_TRAFFIC = {
+    # (stage, storage dtype): (bytes per call, digest of the kernel sources)
+    ("cone_bp_adjoint", "f32"): (17_950_234_449 + 201_420_927,
+                                 "b20824f3b13f4b646730b2456b299cc13758973f035832d03616287bf05010b7"),
+}
+
+
+def kernel_sources_digest():
+    """sha256 over the names and bytes of every file in the package's csrc/."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2410_14900_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -207,13 +231,17 @@ def main():
     dom = max(r["kern"], key=r["kern"].get)
     units, byts = r["work"][dom]
     t = r["kern"][dom] * 1e-3
+    meas = MEASURED_TRAFFIC.get((dom, main_store))
+    traffic = meas[0] if meas and meas[1] == kernel_sources_digest() else None
     if dom.startswith("filter"):
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(byts / t / 1e9, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": byts}
     else:
         ach = units * FLOPS_PER_UNIT[dom] / t / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+                "algorithmic_bytes": byts,
                 "hbm_GBps": round(byts / t / 1e9, 1), "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 5)}
     out = {
         "metric": METRIC,
