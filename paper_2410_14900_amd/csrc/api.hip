@@ -69,6 +69,57 @@ static dc_status validate(const dc_grid* g, const dc_view* views, int32_t n) {
 
 static const int kInterpTX = 32, kInterpTY = 16;
 
+// Largest number of voxel centres the cone adjoint may add into one accumulator
+// (one detector cell in one view); its fixed-point quantum is 2^30 / this of the
+// largest term, so beyond it the adjoint would lose float32 accuracy.
+static const int kMaxCellTerms = 1 << 18;
+
+// Upper bound on the voxel centres whose projection in view w falls in one
+// detector cell [i, i+1) x [j, j+1) of fractional indices.  Points of the cell's
+// frustum are x = a + U (alpha l_x + beta l_y - l_z), U the depth, the cell
+// spanning du/D in alpha and dv/D in beta.  Slice the centre lattice along an
+// axis k over which x_k - a_k keeps one sign on the box.  Two frustum points x1,
+// x2 in one slice differ by U1 (delta - (delta_k / d2_k) d2), d2 = (x2 - a)/U2,
+// delta = d1 - d2 = dalpha l_x + dbeta l_y; along an in-slice axis b that is at
+// most  U_max (du/D |l_x,b - t l_x,k| + dv/D |l_y,b - t l_y,k|),
+// t = (x2_b - a_b)/(x2_k - a_k), whose extremes over the box (a linear-fractional
+// function with a denominator of fixed sign) sit at its corners.  A slice thus
+// holds at most (floor(E_b/v_b)+1)(floor(E_c/v_c)+1) centres and the box has
+// n_k slices; the smallest such product over the admissible axes is the bound.
+static double cell_terms_bound(const dc_grid* g, const dc_view& w, double D,
+                               const double X0[3], double umax) {
+  const int n[3] = {g->nx, g->ny, g->nz};
+  const double vs[3] = {g->vx, g->vy, g->vz};
+  double corner[8][3];
+  for (int c = 0; c < 8; ++c)
+    for (int k = 0; k < 3; ++k) corner[c][k] = X0[k] + ((c >> k) & 1) * (n[k] - 1) * vs[k] - w.src[k];
+  double best = 1e300;
+  for (int k = 0; k < 3; ++k) {
+    bool pos = true, neg = true;
+    for (int c = 0; c < 8; ++c) {
+      pos = pos && corner[c][k] > 0.0;
+      neg = neg && corner[c][k] < 0.0;
+    }
+    if (!pos && !neg) continue;   // the source lies within the box's extent along k
+    double count = n[k];
+    for (int b = 0; b < 3; ++b) {
+      if (b == k) continue;
+      double tmin = 1e300, tmax = -1e300;
+      for (int c = 0; c < 8; ++c) {
+        const double t = corner[c][b] / corner[c][k];
+        tmin = std::min(tmin, t);
+        tmax = std::max(tmax, t);
+      }
+      const double sx = std::max(std::fabs(w.ex[b] - tmin * w.ex[k]), std::fabs(w.ex[b] - tmax * w.ex[k]));
+      const double sy = std::max(std::fabs(w.ey[b] - tmin * w.ey[k]), std::fabs(w.ey[b] - tmax * w.ey[k]));
+      const double E = umax * (g->du / D * sx + g->dv / D * sy);
+      count *= std::floor(E / vs[b] * (1.0 + 1e-9)) + 1.0;
+    }
+    best = std::min(best, count);
+  }
+  return best;
+}
+
 static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, Plan* p) {
   p->grid = *g;
   p->n_views = n;
@@ -134,7 +185,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
 
   std::vector<float> vf(4 * n), rmax2(n);
   std::vector<double> proj(12 * n);
-  double umax_all = 0.0;
+  double max_cell_terms = 0.0;
   const double X0[3] = {-0.5 * (g->nx - 1) * g->vx + g->ox, -0.5 * (g->ny - 1) * g->vy + g->oy,
                         -0.5 * (g->nz - 1) * g->vz + g->oz};
   const double vs[3] = {g->vx, g->vy, g->vz};
@@ -172,20 +223,16 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
       umax = std::max(umax, den * D);
     }
     rmax2[v] = (float)((D / umin) * (D / umin) * (1.0 + 1e-6));
-    umax_all = std::max(umax_all, umax / D);
+    max_cell_terms = std::max(max_cell_terms, cell_terms_bound(g, w, D, X0, umax));
     P[7] = dot3(rel0, w.ex) / g->du + 0.5 * (g->nu - 1) * dn0;
     P[11] = dot3(rel0, w.ey) / g->dv + 0.5 * (g->nv - 1) * dn0;
   }
 
-  // voxels that can share one pixel cell in a view: per slice along any axis the
-  // cell's preimage spans at most sqrt(3) * pitch * U/D in each in-slice direction
-  {
-    const double vmin = std::min(g->vx, std::min(g->vy, g->vz));
-    const double cell = std::sqrt(3.0) * std::max(g->du, g->dv) * umax_all / vmin;
-    const double per_axis = std::ceil(cell) + 1.0;
-    const double n_slices = std::max(g->nx, std::max(g->ny, g->nz));
-    p->cone_max_terms = (int)std::min(1e8, n_slices * per_axis * per_axis);
-  }
+  if (max_cell_terms > (double)kMaxCellTerms)
+    return fail(DC_ENOTSUP, "up to " + std::to_string((long long)max_cell_terms) +
+                                " voxel centres can project into one detector cell (limit " +
+                                std::to_string(kMaxCellTerms) + "); the detector is too coarse for the voxel grid");
+  p->cone_max_terms = (int)std::max(1.0, max_cell_terms);
   // largest backprojection block footprint (same box rule as the kernel) ->
   // how many pixels each of the 256 threads stages per view
   {

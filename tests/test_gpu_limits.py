@@ -1,0 +1,111 @@
+"""GPU parity at the library's size limits: the longest sinogram row it accepts
+(n_s = 4096, staged in LDS by the 2D kernels) and the deepest volume (nz = 1024,
+64 slabs of 16 slices in the cone adjoint), and the single-view case, each
+against the float64 oracle.  Sizes one above each limit are rejected on the
+host before anything is enqueued.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pipeline as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def host(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_14900_amd as P
+    return P
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def long_rows():
+    # 1024^2 detector at 0.5 mm, 4096 bins at 0.2 mm (819 mm > the 724 mm diagonal)
+    return (synth.Grid(nu=1024, nv=1024, du=0.5, dv=0.5, n_theta=16, n_s=4096, ds=0.2,
+                       nx=8, ny=8, nz=8, vx=1.0, vy=1.0, vz=1.0),
+            synth.sinusoid_orbit(2, 750.0, 1200.0))
+
+
+def deep_volume(n_views=5):
+    # 1024 slices of 0.3 mm on a 256^2 detector at 2 mm; 5 views = one full and one partial view group
+    return (synth.Grid(nu=256, nv=256, du=2.0, dv=2.0, n_theta=20, n_s=synth.radon_bins(256, 256), ds=2.0,
+                       nx=12, ny=12, nz=1024, vx=1.0, vy=1.0, vz=0.3),
+            synth.sinusoid_orbit(n_views, 750.0, 1200.0))
+
+
+def test_longest_sinogram_rows(P):
+    g, views = long_rows()
+    print("\n[gpu limits] n_s = 4096", g.as_dict(), flush=True)
+    plan = P.Plan(g, views)
+    V = len(views)
+    x = synth.rand_array((V, g.nv, g.nu), 41, 0.0, 1.0)
+    R = torch.empty((V, g.n_theta, g.n_s), device="cuda")
+    P.dc_weight_radon(plan, dev(x), R)
+    assert rel(host(R), O.weight_radon(x.astype(np.float64), g, views)) < TOL32
+    H = synth.rand_array((V, g.n_theta, g.n_s), 42)
+    gF = torch.empty((V, g.nv, g.nu), device="cuda")
+    P.dc_detector_bp(plan, dev(H), gF)
+    assert rel(host(gF), O.detector_bp(H.astype(np.float64), g)) < TOL32
+    GH = torch.empty((V, g.n_theta, g.n_s), device="cuda")
+    P.dc_detector_bp_adjoint(plan, dev(x), GH)
+    assert rel(host(GH), O.detector_bp_adjoint(x.astype(np.float64), g)) < TOL32
+    M = synth.rand_array((V, g.n_theta, g.n_s), 43, 0.0, 1.0)
+    Hf = torch.empty_like(R)
+    P.dc_filter(plan, dev(H), dev(M), Hf)
+    ref = O.filter_stack(H.astype(np.float64), M.astype(np.float64), g, views)
+    assert rel(host(Hf), ref) < TOL32
+
+
+def test_deepest_volume(P):
+    g, views = deep_volume()
+    print("\n[gpu limits] nz = 1024", g.as_dict(), flush=True)
+    plan = P.Plan(g, views)
+    V = len(views)
+    gF = synth.rand_array((V, g.nv, g.nu), 44)
+    f = torch.empty((g.nz, g.ny, g.nx), device="cuda")
+    P.dc_cone_bp(plan, dev(gF), f)
+    assert rel(host(f), O.cone_bp(gF.astype(np.float64), g, views)) < TOL32
+    Gf, fr = synth.rand_array((g.nz, g.ny, g.nx), 45), synth.rand_array((g.nz, g.ny, g.nx), 46)
+    GgF = torch.empty((V, g.nv, g.nu), device="cuda")
+    P.dc_cone_bp_adjoint(plan, dev(Gf), GgF, f_relu=dev(fr))
+    ref = O.cone_bp_adjoint(Gf.astype(np.float64), g, views, relu_f=fr)
+    assert rel(host(GgF), ref) < TOL32
+
+
+def test_single_view_chain(P):
+    g, views = deep_volume(1)
+    plan = P.Plan(g, views)
+    gp = synth.rand_array((1, g.nv, g.nu), 47, 0.0, 1.0)
+    M = np.full((1, g.n_theta, g.n_s), 0.5, np.float32)
+    f = P.reconstruct(plan, dev(M), g=dev(gp))
+    ref = O.reconstruct(gp.astype(np.float64), M.astype(np.float64), g, views)
+    assert rel(host(f), ref) < TOL32
+
+
+def test_one_above_each_limit_is_rejected(P):
+    import dataclasses
+    g, views = long_rows()
+    with pytest.raises(P.DcError, match="DC_ESHAPE"):
+        P.Plan(dataclasses.replace(g, n_s=4097), views)
+    g, views = deep_volume()
+    with pytest.raises(P.DcError, match="DC_ESHAPE"):
+        P.Plan(dataclasses.replace(g, nz=1025), views)

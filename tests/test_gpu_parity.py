@@ -233,6 +233,26 @@ def test_gradient_wrt_M(P, case):
     assert rel(host(Mt.grad), ref) < TOL_GRAD
 
 
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_forward_backward_bit_reproducible(P, case, store):
+    """Two runs of the whole chain (forward, ReLU, backward to dL/dM) give identical bits."""
+    name, g, views, plan = case
+    V = len(views)
+    gp, _ = _projections(g, views)
+    rng = np.random.Generator(np.random.PCG64(4))
+    M = rng.uniform(0.3, 0.7, (V, g.n_theta, g.n_s)).astype(np.float32)
+    target = rng.uniform(0, 1e-3, (g.nz, g.ny, g.nx)).astype(np.float32)
+    dt = torch.float32 if store == "f32" else torch.bfloat16
+    outs = []
+    for _ in range(2):
+        Mt = dev(M).requires_grad_(True)
+        f = P.reconstruct(plan, Mt, g=dev(gp), store_dtype=dt, relu=True)
+        ((f - dev(target)) ** 2).sum().backward()
+        outs.append((f.detach().clone(), Mt.grad.clone()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
 def test_view_ranges_and_empty_range(P, case):
     name, g, views, plan = case
     V = len(views)
