@@ -66,6 +66,9 @@ __global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img
 }
 
 static constexpr int kSplatKC = 8;   // max angles per workgroup (registers hold one t per angle)
+static constexpr int kSplatPre = 8;   // pixels loaded ahead along a line
+static constexpr float kRoundMagic = 12582912.0f;       // 1.5 * 2^23
+static constexpr unsigned kRoundMagicBits = 0x4B400000u;  // its bit pattern
 
 template <typename Tin, typename Tout, bool WCOS, bool CHECKED>
 __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout* __restrict__ out, KGrid g,
@@ -99,13 +102,15 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
   }
   __syncthreads();
   const float vmax = __uint_as_float(vmax_bits[v]);
-  // quantum: |a| per bin stays below 2^31 - 1 with max_terms contributions
-  const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
+  // quantum: |a| per bin stays below 2^31 - 1 with max_terms contributions, and
+  // every term below 2^21 so the rounding below is exact
+  const float qmax = fminf(floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f), 2097152.0f);
   const float S = vmax > 0.f ? qmax / vmax : 0.f;
   // Threads own whole lines of pixels (columns when the angles spread rows,
   // rows otherwise) and walk them; t advances by an exact fixed-point step, so
   // the bin index is the high word and the fraction the low word, with a
-  // rounding drift below 2^-33 bin per step.
+  // rounding drift below 2^-33 bin per step.  The high word also carries the
+  // angle's LDS row offset (kk * row + 1), so it is the accumulator index itself.
   const int n_lines = colmajor ? g.nv : g.nu;
   const int n_steps = colmajor ? g.nu : g.nv;
   for (int line = threadIdx.x; line < n_lines; line += blockDim.x) {
@@ -115,32 +120,56 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
       if (kk < kn) {
         const double t0 = colmajor ? fma((double)line, sB[kk], sC[kk]) : fma((double)line, sA[kk], sC[kk]);
         const double fl = floor(t0);
-        t[kk] = ((long long)(int)fl << 32) + (long long)(unsigned)((t0 - fl) * 4294967296.0);
+        t[kk] = ((long long)((int)fl + kk * row + 1) << 32) + (long long)(unsigned)((t0 - fl) * 4294967296.0);
       } else {
         t[kk] = 0;
       }
     }
-    for (int p = 0; p < n_steps; ++p) {
-      const int i = colmajor ? p : line, j = colmajor ? line : p;
-      float x = to_f32(im[j * g.nu + i]);
-      if (WCOS) {
-        const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-        x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
-      }
-      const float xs = x * S;
-      const int qa = (int)rintf(xs);
-      const unsigned sa = (unsigned)(qa >> 31);        // sign extension of qa into the high word
-      const float xs2 = xs * 2.3283064365386963e-10f;  // xs * 2^-32
+    // the next kSplatPre pixels of the line are loaded while the current ones
+    // are deposited, so each wave keeps several loads in flight
+    const Tin* base = colmajor ? im + (size_t)line * g.nu : im + line;
+    const int pitch = colmajor ? 1 : g.nu;
+    Tin xb[kSplatPre];   // raw storage values, converted at use
 #pragma unroll
-      for (int kk = 0; kk < kSplatKC; ++kk) {
-        if (kk < kn) {
-          const int m = (int)(t[kk] >> 32);
-          const unsigned lo = (unsigned)t[kk];
-          const int qb = (int)rintf(xs2 * (float)lo);
-          const unsigned long long word =
-              ((unsigned long long)((unsigned)qb + sa) << 32) | (unsigned long long)(unsigned)qa;
-          if (!CHECKED || (unsigned)(m + 1) <= (unsigned)ns) atomicAdd(acc + kk * row + m + 1, word);
-          t[kk] += sStep[kk];
+    for (int q = 0; q < kSplatPre; ++q) xb[q] = q < n_steps ? base[(size_t)q * pitch] : Tin{};
+    for (int p0 = 0; p0 < n_steps; p0 += kSplatPre) {
+      Tin xc[kSplatPre];
+#pragma unroll
+      for (int q = 0; q < kSplatPre; ++q) xc[q] = xb[q];
+      if (p0 + kSplatPre < n_steps) {
+#pragma unroll
+        for (int q = 0; q < kSplatPre; ++q) {
+          const int pn = p0 + kSplatPre + q;
+          xb[q] = pn < n_steps ? base[(size_t)pn * pitch] : Tin{};
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kSplatPre; ++q) {
+        const int p = p0 + q;
+        if (p >= n_steps) break;
+        const int i = colmajor ? p : line, j = colmajor ? line : p;
+        float x = to_f32(xc[q]);
+        if (WCOS) {
+          const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
+          x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+        }
+        const float xs = x * S;
+        // Integer rounding without conversion instructions: adding 1.5 * 2^23
+        // leaves round-to-nearest-even(v) in the low mantissa bits for |v| < 2^22.
+        const int qa = (int)(__float_as_uint(xs + kRoundMagic) - kRoundMagicBits);
+        // high word = qb + sign extension of qa, taken from the same trick
+        const unsigned hbias = kRoundMagicBits - (unsigned)(qa >> 31);
+        const float xs2 = xs * 2.3283064365386963e-10f;  // xs * 2^-32
+#pragma unroll
+        for (int kk = 0; kk < kSplatKC; ++kk) {
+          if (kk < kn) {
+            const unsigned idx = (unsigned)(t[kk] >> 32);  // kk * row + m + 1
+            const unsigned lo = (unsigned)t[kk];
+            const unsigned hi = __float_as_uint(fmaf(xs2, (float)lo, kRoundMagic)) - hbias;
+            const unsigned long long word = ((unsigned long long)hi << 32) | (unsigned long long)(unsigned)qa;
+            if (!CHECKED || idx - (unsigned)(kk * row) <= (unsigned)ns) atomicAdd(acc + idx, word);
+            t[kk] += sStep[kk];
+          }
         }
       }
     }
