@@ -25,6 +25,8 @@
 namespace dc {
 
 static constexpr int kBX = 16, kBY = 16, kZC = 8;
+static constexpr float kRoundMagic = 12582912.0f;         // 1.5 * 2^23
+static constexpr unsigned kRoundMagicBits = 0x4B400000u;  // its bit pattern
 
 struct ColumnMap {
   float den, dden;   // den = U/D at the segment start and its z step
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   __syncthreads();
   const int nrows = sNL * g.ny;
   const int plane = g.nx * g.ny;   // volumes are below 2^31 voxels (checked by the plan)
-  const float qmax = floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f);
+  const float qmax = fminf(floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f), 2097152.0f);
   const float gabs = __uint_as_float(*gmax_bits);
   float S[kFV];
 #pragma unroll
@@ -453,12 +455,17 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
             const float fu = u - fu0, fv = wv - fw0;
             const float gs = x * rr * rr * Sw;
             const float gu = gs * fu;
-            const int qa = (int)rintf(gs), qb = (int)rintf(gu);
-            const int qc = (int)rintf(gs * fv), qe = (int)rintf(gu * fv);
-            const unsigned long long w1 =
-                ((unsigned long long)((unsigned)qb + (unsigned)(qa >> 31)) << 32) | (unsigned)qa;
-            const unsigned long long w2 =
-                ((unsigned long long)((unsigned)qe + (unsigned)(qc >> 31)) << 32) | (unsigned)qc;
+            // Integer rounding without conversion instructions: adding 1.5 * 2^23
+            // leaves round-to-nearest-even(v) in the low mantissa bits for
+            // |v| < 2^22 (every term is below 2^21), and the fused forms round
+            // the products gs fu, gs fv, gu fv once.  The high words take the
+            // sign extension of the low ones through their bias.
+            const int qa = (int)(__float_as_uint(gs + kRoundMagic) - kRoundMagicBits);
+            const int qc = (int)(__float_as_uint(fmaf(gs, fv, kRoundMagic)) - kRoundMagicBits);
+            const unsigned hb = __float_as_uint(fmaf(gs, fu, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qa >> 31));
+            const unsigned he = __float_as_uint(fmaf(gu, fv, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qc >> 31));
+            const unsigned long long w1 = ((unsigned long long)hb << 32) | (unsigned)qa;
+            const unsigned long long w2 = ((unsigned long long)he << 32) | (unsigned)qc;
             atomicAdd(ab + lj * kFW + li, w1);
             atomicAdd(ce + lj * kFW + li, w2);
           }
