@@ -67,7 +67,6 @@ static dc_status validate(const dc_grid* g, const dc_view* views, int32_t n) {
   return DC_OK;
 }
 
-static const int kInterpTX = 32, kInterpTY = 16;
 
 // Largest number of voxel centres the cone adjoint may add into one accumulator
 // (one detector cell in one view); its fixed-point quantum is 2^30 / this of the
@@ -131,7 +130,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
 
   const int K = g->n_theta;
   std::vector<double> ang(3 * K);
-  std::vector<float> angf(4 * K), trig(2 * K);
+  std::vector<float> trig(2 * K);
   const double x0 = -0.5 * (g->nu - 1) * g->du, y0 = -0.5 * (g->nv - 1) * g->dv;
   int wl = 0;
   for (int kk = 0; kk < K; ++kk) {
@@ -139,9 +138,8 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
     double A = g->du * c / g->ds, B = g->dv * s / g->ds;
     double C = (x0 * c + y0 * s) / g->ds + 0.5 * (g->n_s - 1);
     ang[3 * kk] = A; ang[3 * kk + 1] = B; ang[3 * kk + 2] = C;
-    angf[4 * kk] = (float)A; angf[4 * kk + 1] = (float)B; angf[4 * kk + 2] = (float)C; angf[4 * kk + 3] = 0.f;
     trig[2 * kk] = (float)c; trig[2 * kk + 1] = (float)s;
-    int w = (int)std::ceil((kInterpTX - 1) * std::fabs(A) + (kInterpTY - 1) * std::fabs(B)) + 4;
+    int w = (int)std::ceil((interp_tile(0) - 1) * std::fabs(A) + (interp_tile(1) - 1) * std::fabs(B)) + 4;
     if (w > wl) wl = w;
   }
   p->interp_wl = wl;
@@ -271,7 +269,6 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
   };
   hipError_t e;
   if ((e = up((void**)&p->d_ang, ang.data(), ang.size() * sizeof(double))) != hipSuccess ||
-      (e = up((void**)&p->d_angf, angf.data(), angf.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_trig, trig.data(), trig.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_view, vf.data(), vf.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
@@ -285,7 +282,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
 }
 
 static void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_ang,    p->d_angf,   p->d_trig,    p->d_view,  p->d_proj,
+  void* ptrs[] = {p->d_ang,    p->d_trig,    p->d_view,  p->d_proj,
                   p->d_rmax2,  p->d_chunks, p->d_scratch, p->d_masked};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);

@@ -55,7 +55,6 @@ struct Plan {
   // per angle k (float64): A_k = du cos mu/ds, B_k = dv sin mu/ds,
   // C_k = fractional bin index of pixel (0,0)      -> t = i A + j B + C
   double* d_ang = nullptr;       // [n_theta][3]
-  float* d_angf = nullptr;       // [n_theta][4]  (A, B, C, 0) rounded once
   float* d_trig = nullptr;       // [n_theta][2]  cos mu, sin mu
   // per view (float32): D, t.l_x/(4 pi^2 D), t.l_y/(4 pi^2 D), t.l_z/(4 pi^2 D^2)
   float* d_view = nullptr;       // [V][4]
@@ -86,6 +85,8 @@ void set_error(const std::string& msg);
 
 // backprojection voxel block edge along axis 0/1/2 (cone.hip)
 int cone_bp_block(int axis);
+// pixel tile of the detector-BP (interpolation) kernel along u (axis 0) and v (axis 1)
+int interp_tile(int axis);
 
 // scratch helpers (radon2d.hip)
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
