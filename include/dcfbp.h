@@ -29,7 +29,7 @@
  *
  * Layouts (contiguous, row-major, last index fastest):
  *   g, gF, Gg, GgF : [V][nv][nu]     R, H, M, GM, GR, GH : [V][n_theta][n_s]
- *   f, Gf          : [nz][ny][nx]
+ *   f, Gf          : [nz][ny][nx]    ([S][nz][ny][nx] for a plan of S samples)
  * Every stage call takes pointers to the FULL per-view arrays and processes the
  * view range [v0, v0+nv); volumes are shared by all views.
  *
@@ -39,9 +39,9 @@
  * dtype, alignment, view range); dc_last_error() gives a thread-local message.
  * A fault inside a kernel surfaces at the caller's next synchronisation.
  * Ownership: the caller owns every array; the plan owns its small device
- * tables (immutable after creation), a scratch word per view that
+ * tables (immutable after creation), a scratch word per view and per sample that
  * dc_weight_radon, dc_detector_bp_adjoint and dc_cone_bp_adjoint use for their
- * fixed-point scales, and one volume-sized float32 buffer into which
+ * fixed-point scales, and one volume-sized float32 buffer per sample into which
  * dc_cone_bp_adjoint writes the ReLU-masked gradient; stage calls on one plan
  * must therefore be ordered on one stream (use one plan per concurrent stream).  Plans must be created before any stream
  * capture that uses them; stage calls enqueue kernels only (no memset, no
@@ -102,11 +102,26 @@ dc_status dc_validate(const dc_grid* grid, const dc_view* views, int32_t n_views
  * here, never in a stage call).  flags must be 0.  *out is set only on DC_OK. */
 dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_views,
                          uint32_t flags, dc_plan* out);
+/* Batched plan: n_samples scans that share one grid, each with its own orbit
+ * (eq. 12 applied to every scan; the views of different scans never mix).  The
+ * views of sample s are views[first_view[s] .. first_view[s+1]) (first_view has
+ * n_samples + 1 entries, starts at 0, ends at n_views, strictly increasing).
+ * Per-view arrays (g, R, M, H, gF and their gradients) hold all samples' views
+ * back to back; volumes (f, Gf, f_relu) hold one [nz][ny][nx] block per sample,
+ * in sample order, so every stage call serves all samples with one launch per
+ * kernel.  A view range [v0, v0+nv) may span samples: dc_cone_bp writes the
+ * volumes of the samples it meets (for nv = 0, the sample holding view v0, the
+ * last one when v0 = n_views) and leaves the others untouched; dc_cone_bp_adjoint
+ * reads each view's own sample volume.  dc_plan_create is n_samples = 1. */
+dc_status dc_plan_create_batched(const dc_grid* grid, const dc_view* views, int32_t n_views,
+                                 const int32_t* first_view, int32_t n_samples, uint32_t flags,
+                                 dc_plan* out);
 dc_status dc_plan_destroy(dc_plan plan);
 /* Thread-local text of the last error (empty string if none). */
 const char* dc_last_error(void);
-/* Size queries used by bindings: views, and the grid the plan was built with. */
+/* Size queries used by bindings: views, samples, and the grid the plan was built with. */
 int32_t dc_plan_n_views(dc_plan plan);
+int32_t dc_plan_n_samples(dc_plan plan);
 dc_status dc_plan_grid(dc_plan plan, dc_grid* out);
 
 /* Stage 1, eq. 7 (integrate first): R[v] = (du dv/ds) sum_p w_cos(p) g[v](p) Lambda((s_p,k - s_m)/ds),

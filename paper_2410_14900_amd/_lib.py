@@ -45,9 +45,12 @@ _i, _p, _vp = c_int32, c_void_p, c_void_p
 SIGNATURES = {
     "dc_validate": (_i, [POINTER(DcGrid), POINTER(DcView), _i]),
     "dc_plan_create": (_i, [POINTER(DcGrid), POINTER(DcView), _i, c_uint32, POINTER(c_void_p)]),
+    "dc_plan_create_batched": (_i, [POINTER(DcGrid), POINTER(DcView), _i, POINTER(c_int32), _i, c_uint32,
+                                   POINTER(c_void_p)]),
     "dc_plan_destroy": (_i, [_p]),
     "dc_last_error": (c_char_p, []),
     "dc_plan_n_views": (_i, [_p]),
+    "dc_plan_n_samples": (_i, [_p]),
     "dc_plan_grid": (_i, [_p, POINTER(DcGrid)]),
     "dc_weight_radon": (_i, [_p, _vp, _vp, _i, _i, _i, _vp]),
     "dc_weight_radon_adjoint": (_i, [_p, _vp, _i, _vp, _i, _i, _vp]),

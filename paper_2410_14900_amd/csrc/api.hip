@@ -119,9 +119,12 @@ static double cell_terms_bound(const dc_grid* g, const dc_view& w, double D,
   return best;
 }
 
-static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, Plan* p) {
+static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, const int32_t* first,
+                            int32_t n_samples, Plan* p) {
   p->grid = *g;
   p->n_views = n;
+  p->n_samples = n_samples;
+  p->first.assign(first, first + n_samples + 1);
   KGrid& k = p->kg;
   k.nu = g->nu; k.nv = g->nv; k.n_theta = g->n_theta; k.n_s = g->n_s;
   k.nx = g->nx; k.ny = g->ny; k.nz = g->nz;
@@ -274,19 +277,35 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, P
       (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
       (e = up((void**)&p->d_rmax2, rmax2.data(), rmax2.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess ||
-      (e = hipMalloc((void**)&p->d_scratch, (n + 1) * sizeof(unsigned))) != hipSuccess ||
-      (e = hipMalloc((void**)&p->d_masked, (size_t)g->nx * g->ny * g->nz * sizeof(float))) != hipSuccess)
+      (e = up((void**)&p->d_first, p->first.data(), p->first.size() * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_scratch, (n + n_samples) * sizeof(unsigned))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_masked, (size_t)n_samples * g->nx * g->ny * g->nz * sizeof(float))) !=
+          hipSuccess)
     return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP,
                 std::string("plan upload: ") + hipGetErrorString(e));
   return DC_OK;
 }
 
 static void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_ang,    p->d_trig,    p->d_view,  p->d_proj,
-                  p->d_rmax2,  p->d_chunks, p->d_scratch, p->d_masked};
+  void* ptrs[] = {p->d_ang,    p->d_trig,   p->d_view,    p->d_proj,   p->d_rmax2,
+                  p->d_chunks, p->d_first,  p->d_scratch, p->d_masked};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
+}
+
+void sample_span(const Plan& p, int v0, int nv, int* s_lo, int* s_hi) {
+  // last sample whose first view is <= v
+  auto sample_of = [&](int v) {
+    int lo = 0, hi = p.n_samples - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (p.first[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  *s_lo = sample_of(v0);
+  *s_hi = nv > 0 ? sample_of(v0 + nv - 1) : *s_lo;
 }
 
 // ---------------------------------------------------------- call checking
@@ -337,23 +356,44 @@ dc_status dc_validate(const dc_grid* grid, const dc_view* views, int32_t n_views
   return validate(grid, views, n_views);
 }
 
-dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_views, uint32_t flags,
-                         dc_plan* out) {
+static dc_status create(const dc_grid* grid, const dc_view* views, int32_t n_views, const int32_t* first,
+                        int32_t n_samples, uint32_t flags, dc_plan* out) {
   if (!out) return fail(DC_EINVAL, "null output plan pointer");
   if (flags != 0) return fail(DC_EINVAL, "flags must be 0");
   DC_TRY(validate(grid, views, n_views));
+  if (n_samples < 1) return fail(DC_ESHAPE, "n_samples must be >= 1");
+  if (!first) return fail(DC_EINVAL, "null first_view");
+  if (first[0] != 0 || first[n_samples] != n_views)
+    return fail(DC_ESHAPE, "first_view must start at 0 and end at n_views");
+  for (int s = 0; s < n_samples; ++s)
+    if (first[s + 1] <= first[s])
+      return fail(DC_ESHAPE, "sample " + std::to_string(s) + " has no views (first_view must increase)");
+  if ((long long)((grid->nz + cone_bp_block(2) - 1) / cone_bp_block(2)) * n_samples > 65535)
+    return fail(DC_ENOTSUP, "too many samples for this volume depth (the backprojection grid holds "
+                            "(nz / " + std::to_string(cone_bp_block(2)) + ") x samples <= 65535 blocks)");
   Plan* p = new Plan();
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(DC_EHIP, "no HIP device");
   }
-  dc_status st = build_plan(grid, views, n_views, p);
+  dc_status st = build_plan(grid, views, n_views, first, n_samples, p);
   if (st != DC_OK) {
     free_plan(p);
     return st;
   }
   *out = reinterpret_cast<dc_plan>(p);
   return DC_OK;
+}
+
+dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_views, uint32_t flags,
+                         dc_plan* out) {
+  const int32_t first[2] = {0, n_views};
+  return create(grid, views, n_views, first, 1, flags, out);
+}
+
+dc_status dc_plan_create_batched(const dc_grid* grid, const dc_view* views, int32_t n_views,
+                                 const int32_t* first_view, int32_t n_samples, uint32_t flags, dc_plan* out) {
+  return create(grid, views, n_views, first_view, n_samples, flags, out);
 }
 
 dc_status dc_plan_destroy(dc_plan plan) {
@@ -363,6 +403,7 @@ dc_status dc_plan_destroy(dc_plan plan) {
 }
 
 int32_t dc_plan_n_views(dc_plan plan) { return plan ? reinterpret_cast<Plan*>(plan)->n_views : -1; }
+int32_t dc_plan_n_samples(dc_plan plan) { return plan ? reinterpret_cast<Plan*>(plan)->n_samples : -1; }
 
 dc_status dc_plan_grid(dc_plan plan, dc_grid* out) {
   if (!plan || !out) return fail(DC_EINVAL, "null argument");

@@ -100,11 +100,20 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
 template <typename T, int STAGE>
 __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
-                                                 int nv) {
+                                                 int nv, const int* __restrict__ first, int s_lo, int nzb) {
   constexpr int kTile = STAGE > 0 ? 256 * STAGE : 1;
   __shared__ float tile[2][kTile];
   const int tid = threadIdx.y * kBX + threadIdx.x;
-  const int bx0 = blockIdx.x * kBX, by0 = blockIdx.y * kBY, bz0 = blockIdx.z * kZC;
+  // grid z = (sample, z-block): this workgroup sums the views of its sample that
+  // lie in [v0, v0 + nv) into that sample's volume
+  const int zb = blockIdx.z % nzb, smp = s_lo + blockIdx.z / nzb;
+  {
+    const int vb = max(v0, first[smp]), ve = min(v0 + nv, first[smp + 1]);
+    v0 = vb;
+    nv = max(0, ve - vb);
+  }
+  f += (size_t)smp * g.nx * g.ny * g.nz;
+  const int bx0 = blockIdx.x * kBX, by0 = blockIdx.y * kBY, bz0 = zb * kZC;
   const int bx1 = min(g.nx, bx0 + kBX) - 1, by1 = min(g.ny, by0 + kBY) - 1, bz1 = min(g.nz, bz0 + kZC) - 1;
   const int ix = bx0 + threadIdx.x, iy = by0 + threadIdx.y, iz0 = bz0;
   float acc[kZC];
@@ -260,6 +269,12 @@ __global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf
                                                     size_t n, unsigned* __restrict__ out,
                                                     float* __restrict__ masked) {
   __shared__ float red[256];
+  // grid y = sample: one volume of n voxels each
+  const size_t base = (size_t)blockIdx.y * n;
+  Gf += base;
+  if (f_relu) f_relu += base;
+  masked += base;
+  out += blockIdx.y;
   float mx = 0.f;
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
     float x = Gf[q];
@@ -283,9 +298,11 @@ static constexpr int kFMaxLayers = 64;
 static constexpr int kFV = 4;   // consecutive views per workgroup (their frusta nearly coincide)
 
 template <typename Tout>
-__global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g, const double* __restrict__ proj,
-                                                 const float* __restrict__ rmax2, int v0, int nv, int tiles_u,
-                                                 int n_tiles, int max_terms, const unsigned* __restrict__ gmax_bits) {
+__global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
+                                                 const double* __restrict__ proj, const float* __restrict__ rmax2,
+                                                 int v0, int nv, int tiles_u, int n_tiles, int max_terms,
+                                                 const unsigned* __restrict__ gmax_bits,
+                                                 const int* __restrict__ first, int s_lo, int s_hi, int ngroups) {
   __shared__ double sL[kFV][4][4], sNegInvA[kFV][4];
   __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
   __shared__ int sScan[256];
@@ -297,12 +314,24 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   // tile and sweeps it through all view groups, so the ~100 workgroups resident
   // on an XCD share one tile, whose voxels over all views (a thin annulus)
   // stay in that XCD's L2.
-  const int ngroups = (nv + kFV - 1) / kFV;
   const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
   const int tile = xcd + 8 * (k / ngroups);
   if (tile >= n_tiles) return;
-  const int va = v0 + (k % ngroups) * kFV;
-  const int nvw = min(kFV, v0 + nv - va);
+  // view groups of up to kFV consecutive views, restarted at every sample's first
+  // view, so a group reads one sample's volume
+  int grp = k % ngroups, smp = s_lo, va = v0, nvw = 0;
+  for (; smp <= s_hi; ++smp) {
+    const int vb = max(v0, first[smp]), ve = min(v0 + nv, first[smp + 1]);
+    const int ng = (ve - vb + kFV - 1) / kFV;
+    if (grp < ng) {
+      va = vb + grp * kFV;
+      nvw = min(kFV, ve - va);
+      break;
+    }
+    grp -= ng;
+  }
+  if (nvw <= 0) return;
+  Gf += (size_t)smp * g.nx * g.ny * g.nz;
   const int ti = tile % tiles_u, tj = tile / tiles_u;
   const int i0 = ti * kFTI, i1 = min(g.nu, i0 + kFTI);
   const int j0 = tj * kFTJ, j1 = min(g.nv, j0 + kFTJ);
@@ -354,7 +383,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   const int nrows = sNL * g.ny;
   const int plane = g.nx * g.ny;   // volumes are below 2^31 voxels (checked by the plan)
   const float qmax = fminf(floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f), 2097152.0f);
-  const float gabs = __uint_as_float(*gmax_bits);
+  const float gabs = __uint_as_float(gmax_bits[smp]);
   float S[kFV];
 #pragma unroll
   for (int w = 0; w < kFV; ++w) {
@@ -503,11 +532,15 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
 
 hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0, int nv,
                           hipStream_t s) {
-  dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + kBY - 1) / kBY, (p.kg.nz + kZC - 1) / kZC);
+  int s_lo, s_hi;
+  sample_span(p, v0, nv, &s_lo, &s_hi);
+  const int nzb = (p.kg.nz + kZC - 1) / kZC;
+  dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + kBY - 1) / kBY, nzb * (s_hi - s_lo + 1));
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
-#define DC_BP(ST) \
-  hipLaunchKernelGGL((k_cone_bp<T, ST>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, relu, v0, nv)
+#define DC_BP(ST)                                                                                          \
+  hipLaunchKernelGGL((k_cone_bp<T, ST>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, relu, \
+                     v0, nv, p.d_first, s_lo, nzb)
     switch (p.bp_stage) {
       case 4: DC_BP(4); break;
       case 8: DC_BP(8); break;
@@ -525,20 +558,29 @@ int cone_bp_block(int axis) { return axis == 0 ? kBX : axis == 1 ? kBY : kZC; }
 hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, void* GgF, dc_dtype tF, int v0,
                           int nv, hipStream_t s) {
   const int tiles_u = (p.kg.nu + kFTI - 1) / kFTI, tiles_v = (p.kg.nv + kFTJ - 1) / kFTJ;
-  unsigned* gmax = p.d_scratch + p.n_views;
-  hipError_t e = launch_zero_u32(gmax, 1, s);
+  int s_lo, s_hi;
+  sample_span(p, v0, nv, &s_lo, &s_hi);
+  const int n_smp = s_hi - s_lo + 1;
+  unsigned* gmax = p.d_scratch + p.n_views;   // one word per sample
+  hipError_t e = launch_zero_u32(gmax + s_lo, n_smp, s);
   if (e != hipSuccess) return e;
   const size_t n = (size_t)p.kg.nx * p.kg.ny * p.kg.nz;
   const int blocks = (int)std::min<size_t>(2048, (n + 255) / 256);
-  hipLaunchKernelGGL(k_vol_absmax, dim3(blocks), dim3(256), 0, s, Gf, f_relu, n, gmax, p.d_masked);
+  hipLaunchKernelGGL(k_vol_absmax, dim3(blocks, n_smp), dim3(256), 0, s, Gf + s_lo * n,
+                     f_relu ? f_relu + s_lo * n : nullptr, n, gmax + s_lo, p.d_masked + s_lo * n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int n_tiles = tiles_u * tiles_v, ngroups = (nv + kFV - 1) / kFV;
+  int ngroups = 0;
+  for (int smp = s_lo; smp <= s_hi; ++smp) {
+    const int vb = std::max(v0, p.first[smp]), ve = std::min(v0 + nv, p.first[smp + 1]);
+    ngroups += (std::max(0, ve - vb) + kFV - 1) / kFV;
+  }
+  const int n_tiles = tiles_u * tiles_v;
   dim3 grid(8 * ((n_tiles + 7) / 8) * ngroups);
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
     const float* src = f_relu ? p.d_masked : Gf;
     hipLaunchKernelGGL((k_cone_fp<T>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, nv,
-                       tiles_u, n_tiles, p.cone_max_terms, gmax);
+                       tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, s_lo, s_hi, ngroups);
     return hipGetLastError();
   });
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <vector>
 
 #include "dcfbp.h"
 
@@ -67,13 +68,18 @@ struct Plan {
   int bp_stage = 0;              // staged pixels per thread in the backprojection (0: global taps)
   // splat (Radon) work list: angle chunks that stay on one side of the diagonal
   int4* d_chunks = nullptr;      // (k0, count, column_major, 0)
-  // plan-owned scratch: [0, V) per-view max |input| of the splat, [V] max |Gf| of
-  // the cone adjoint (float bits, reduced with integer atomicMax).  Calls on one
-  // plan must therefore be ordered on one stream.
-  unsigned* d_scratch = nullptr; // [V + 1]
+  // samples (scans) of a batched plan: views of sample s are [first[s], first[s+1]);
+  // per-view arrays hold all samples' views, volumes one block per sample
+  int n_samples = 1;
+  std::vector<int> first;        // host copy, [n_samples + 1]
+  int* d_first = nullptr;        // [n_samples + 1]
+  // plan-owned scratch: [0, V) per-view max |input| of the splat, [V, V + S) per-sample
+  // max |Gf| of the cone adjoint (float bits, reduced with integer atomicMax).  Calls
+  // on one plan must therefore be ordered on one stream.
+  unsigned* d_scratch = nullptr; // [V + S]
   // volume-sized scratch for dc_cone_bp_adjoint with a ReLU mask: Gf * [f > 0]
   // is formed once so the gather reads one array instead of two
-  float* d_masked = nullptr;     // [nz][ny][nx]
+  float* d_masked = nullptr;     // [S][nz][ny][nx]
   int n_chunks = 0;
   int splat_kc = 0;              // max angles per chunk
   int splat_max_terms = 0;       // max pixels that share one (angle, bin)
@@ -87,6 +93,10 @@ void set_error(const std::string& msg);
 int cone_bp_block(int axis);
 // pixel tile of the detector-BP (interpolation) kernel along u (axis 0) and v (axis 1)
 int interp_tile(int axis);
+
+// samples whose views meet [v0, v0+nv): s_lo..s_hi; for an empty range the
+// sample holding view v0 (the last one when v0 = V)
+void sample_span(const Plan& p, int v0, int nv, int* s_lo, int* s_hi);
 
 // scratch helpers (radon2d.hip)
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);

@@ -40,19 +40,41 @@ def validate(grid, views):
 
 
 class Plan:
-    """Geometry plan on the current device (small float64-derived tables)."""
+    """Geometry plan on the current device (small float64-derived tables).
 
-    def __init__(self, grid, views):
+    With ``first_view`` (n_samples + 1 increasing view indices) the plan is
+    batched: several scans sharing the grid, views back to back, and volumes of
+    shape (n_samples, nz, ny, nx).  ``Plan.batched(grid, [views, ...])`` builds one
+    from a list of per-scan view sets."""
+
+    def __init__(self, grid, views, first_view=None):
         self.grid = make_grid(grid)
         buf, n = make_views(views)
         h = ctypes.c_void_p()
-        check(_lib.lib().dc_plan_create(ctypes.byref(self.grid), buf, n, 0, ctypes.byref(h)), "dc_plan_create")
+        L = _lib.lib()
+        if first_view is None:
+            check(L.dc_plan_create(ctypes.byref(self.grid), buf, n, 0, ctypes.byref(h)), "dc_plan_create")
+        else:
+            fv = [int(x) for x in first_view]
+            arr = (ctypes.c_int32 * len(fv))(*fv)
+            check(L.dc_plan_create_batched(ctypes.byref(self.grid), buf, n, arr, len(fv) - 1, 0, ctypes.byref(h)),
+                  "dc_plan_create_batched")
         self.handle = h
         self.n_views = n
+        self.n_samples = L.dc_plan_n_samples(h)
+        self.first_view = [0, n] if first_view is None else [int(x) for x in first_view]
         g = self.grid
         self.det_shape = (g.nv, g.nu)
         self.sino_shape = (g.n_theta, g.n_s)
-        self.vol_shape = (g.nz, g.ny, g.nx)
+        self.vol_shape = (g.nz, g.ny, g.nx) if first_view is None else (self.n_samples, g.nz, g.ny, g.nx)
+
+    @classmethod
+    def batched(cls, grid, view_sets):
+        """One plan over several scans (each a view set with ``packed()`` or an [n][15] array)."""
+        parts = [np.ascontiguousarray(v.packed() if hasattr(v, "packed") else v, np.float64).reshape(-1, 15)
+                 for v in view_sets]
+        first = np.concatenate([[0], np.cumsum([len(p) for p in parts])])
+        return cls(grid, np.concatenate(parts), first_view=first)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -62,3 +62,25 @@ def test_plan_create_without_device_fails_cleanly(P):
     g, v = synth.config_geometry("C1", n_views=4)
     with pytest.raises(P.DcError):
         P.Plan(g, v)
+
+
+@pytest.mark.parametrize("first, status", [
+    ([1, 4, 8], "DC_ESHAPE"),      # does not start at 0
+    ([0, 4, 7], "DC_ESHAPE"),      # does not end at n_views
+    ([0, 4, 4, 8], "DC_ESHAPE"),   # an empty sample
+    ([0, 6, 3, 8], "DC_ESHAPE"),   # not increasing
+])
+def test_batched_plan_rejects_bad_sample_lists_before_touching_the_device(P, first, status):
+    g, v = synth.config_geometry("C1", n_views=8)
+    with pytest.raises(P.DcError, match=status):
+        P.Plan(g, v, first_view=first)
+
+
+def test_batched_plan_rejects_more_samples_than_the_backprojection_grid_holds(P):
+    import dataclasses
+    g, v = synth.config_geometry("C1", n_views=8)
+    g = dataclasses.replace(g, nz=1024, vz=0.03)          # 128 z-blocks of 8 slices
+    first = list(range(0, 520)) + [520]                   # 520 one-view samples: 128 * 520 > 65535
+    views = synth.sinusoid_orbit(520, 750.0, 1200.0)
+    with pytest.raises(P.DcError, match="DC_ENOTSUP"):
+        P.Plan(g, views, first_view=first)
