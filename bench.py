@@ -105,6 +105,164 @@ def cpu_baseline(grid, views, n_views=1):
                       "256^3 volume), float64 NumPy, single thread; %.1f s" % (n_views, len(views), dt)}
 
 
+def adam_(M, G, m, v, t, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8):
+    """Adam update of M in place from gradient G, with the step count t kept on the
+    device, in elementwise torch ops only (so the update can sit in a captured graph)."""
+    import torch
+    t.add_(1.0)
+    m.mul_(b1).add_(G, alpha=1.0 - b1)
+    v.mul_(b2).addcmul_(G, G, value=1.0 - b2)
+    bc1 = 1.0 - torch.pow(b1, t)
+    bc2 = 1.0 - torch.pow(b2, t)
+    M.addcdiv_(m / bc1, (v / bc2).sqrt_().add_(eps), value=-lr)
+
+
+class Trainer:
+    """One training step of the DC-FBP network over a plan (one scan or a batch):
+    R = A2d(w_cos g), H = D(W D R), gF = A2d^T H, f = ReLU(cone BP), the MSE
+    gradient, the adjoint chain to dL/dM and an Adam update of M.  Buffers are
+    allocated once, so the step can be captured in a graph."""
+
+    STAGES = ["weight_radon", "filter", "detector_bp", "cone_bp", "cone_bp_adjoint", "detector_bp_adjoint",
+              "filter_adjoint"]
+
+    def __init__(self, P, plan, g, target, store):
+        import torch
+        self.P, self.plan, self.g, self.target = P, plan, g, target
+        V, (K, S), det = plan.n_views, plan.sino_shape, plan.det_shape
+        dev = g.device
+        self.R = torch.empty((V, K, S), device=dev)
+        self.H = torch.empty((V, K, S), device=dev, dtype=store)
+        self.gF = torch.empty((V,) + det, device=dev, dtype=store)
+        self.f = torch.empty(plan.vol_shape, device=dev)
+        self.Gf = torch.empty_like(self.f)
+        self.GgF = torch.empty_like(self.gF)
+        self.GH = torch.empty_like(self.H)
+        self.M = torch.full((V, K, S), 0.5, device=dev)
+        self.GM = torch.empty_like(self.M)
+        self.m, self.v = torch.zeros_like(self.M), torch.zeros_like(self.M)
+        self.t = torch.zeros((), device=dev)
+        self.gscale = 2.0 / target.numel()
+
+    def step(self, timed=None):
+        import torch
+        P, pl = self.P, self.plan
+        run = timed or (lambda name, fn: fn())
+        run("weight_radon", lambda: P.dc_weight_radon(pl, self.g, self.R))
+        run("filter", lambda: P.dc_filter(pl, self.R, self.M, self.H))
+        run("detector_bp", lambda: P.dc_detector_bp(pl, self.H, self.gF))
+        run("cone_bp", lambda: P.dc_cone_bp(pl, self.gF, self.f, relu=True))
+        torch.sub(self.f, self.target, out=self.Gf)
+        self.Gf.mul_(self.gscale)
+        run("cone_bp_adjoint", lambda: P.dc_cone_bp_adjoint(pl, self.Gf, self.GgF, f_relu=self.f))
+        run("detector_bp_adjoint", lambda: P.dc_detector_bp_adjoint(pl, self.GgF, self.GH))
+        run("filter_adjoint", lambda: P.dc_filter_adjoint(pl, self.GH, self.R, self.M, GM=self.GM))
+        adam_(self.M, self.GM, self.m, self.v, self.t)
+
+    def rel_error(self):
+        """Relative L2 error of the current reconstruction against the phantom."""
+        d = (self.f - self.target).double()
+        return float(d.norm() / self.target.double().norm())
+
+
+def time_eager(trainers, steps, warmup, per_stage=False):
+    """ms per step of running every trainer's step once, eagerly; optional per-stage event times."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ev = {s: [] for s in Trainer.STAGES}
+
+    def timed(name, fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        ev[name].append((a, b))
+
+    for _ in range(warmup):
+        for tr in trainers:
+            tr.step()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        for tr in trainers:
+            tr.step(timed if per_stage else None)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    kern = {s: sum(a.elapsed_time(b) for a, b in ev[s]) / len(ev[s]) for s in Trainer.STAGES} if per_stage else None
+    return ms, kern
+
+
+def time_graph(trainer, steps, warmup):
+    """ms per step of replaying the trainer's step captured in one HIP graph."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        trainer.step()                       # warm-up on a side stream before capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        trainer.step()
+    for _ in range(max(0, warmup - 1)):
+        graph.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        graph.replay()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps, graph
+
+
+def batched_c4(P, synth, args):
+    """The batched workload: 8 scans with mixed orbits (3002 views) on the C2 grid.
+    FP32 storage with one plan per scan run eagerly, against BF16 storage with one
+    batched plan whose whole step is one captured graph; same data, same number of
+    steps, reconstruction error of both against the phantoms."""
+    import torch
+    grid, sets, seeds = synth.c4_scans()
+    nvox = grid.nx * grid.ny * grid.nz
+    gs, targets = [], []
+    for views, seed in zip(sets, seeds):
+        ell = synth.random_ellipsoids(20, grid.nx * grid.vx, seed)
+        gs.append(synth.project_ellipsoids(ell, grid, views, device="cuda").float().contiguous())
+        targets.append(synth.voxelize_torch(ell, grid, device="cuda"))
+    Vt = sum(len(v) for v in sets)
+    log("C4 inputs ready:", [len(v) for v in sets], "views")
+    singles = [Trainer(P, P.Plan(grid, v), g, t, torch.float32) for v, g, t in zip(sets, gs, targets)]
+    ms32, _ = time_eager(singles, args.batched_steps, args.warmup)
+    err32 = sum(tr.rel_error() for tr in singles) / len(singles)
+    log("C4 fp32 per-scan eager: %.2f ms/step, mean relative error %.5f" % (ms32, err32))
+    del singles
+    torch.cuda.empty_cache()
+    plan = P.Plan.batched(grid, sets)
+    g = torch.cat(gs)
+    del gs
+    tb = Trainer(P, plan, g, torch.stack(targets), torch.bfloat16)
+    # one eager warm-up step, warmup - 1 untimed and `steps` timed replays: both forms
+    # have taken warmup + steps Adam steps when their errors are compared
+    msbg, _graph = time_graph(tb, args.batched_steps, args.warmup)
+    errbg = sum(float((tb.f[s] - tb.target[s]).double().norm() / tb.target[s].double().norm())
+                for s in range(plan.n_samples)) / plan.n_samples
+    log("C4 bf16 batched graph: %.2f ms/step, mean relative error %.5f" % (msbg, errbg))
+    return {
+        "workload": "C4: 8 scans on the C2 grid (circle 248/496/372, sinusoid 496/248/372, circle+arc 100+360 "
+                    "and 60+250 views; 3002 views), 20 seeded ellipsoids each, no noise",
+        "views": Vt, "samples": len(sets),
+        "fp32_per_scan_eager": {"value": nvox * Vt / (ms32 * 1e-3), "ms_per_step": round(ms32, 3),
+                                "mean_rel_error": round(err32, 6)},
+        "bf16_batched_graph": {"value": nvox * Vt / (msbg * 1e-3), "ms_per_step": round(msbg, 3),
+                               "mean_rel_error": round(errbg, 6)},
+        "speedup": round(ms32 / msbg, 3),
+        "steps": args.batched_steps,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +271,8 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "bf16", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=4)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 8-scan measurement")
+    ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -121,7 +281,6 @@ def main():
               "with one all-reduce of the volume, which is not built).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import synth
     import paper_2410_14900_amd as P
@@ -155,75 +314,28 @@ def main():
     log("inputs ready")
 
     results = {}
-    stream = torch.cuda.current_stream()
     for store in (["f32", "bf16"] if args.dtype == "both" else [args.dtype]):
         sdt = torch.float32 if store == "f32" else torch.bfloat16
-        bpe = 4 if store == "f32" else 2
-        K, S = grid.n_theta, grid.n_s
-        R = torch.empty((V, K, S), device="cuda")
-        H = torch.empty((V, K, S), device="cuda", dtype=sdt)
-        gF = torch.empty((V, grid.nv, grid.nu), device="cuda", dtype=sdt)
-        f = torch.empty((grid.nz, grid.ny, grid.nx), device="cuda")
-        GgF = torch.empty((V, grid.nv, grid.nu), device="cuda", dtype=sdt)
-        GH = torch.empty((V, K, S), device="cuda", dtype=sdt)
-        M = torch.full((V, K, S), 0.5, device="cuda", requires_grad=True)
-        GM = torch.empty((V, K, S), device="cuda")
-        opt = torch.optim.Adam([M], lr=1e-2)
-        stages = ["weight_radon", "filter", "detector_bp", "cone_bp", "cone_bp_adjoint",
-                  "detector_bp_adjoint", "filter_adjoint"]
-        ev = {s: [] for s in stages}
-        loss_box = {}
-
-        def run(record):
-            def timed(name, fn):
-                if record:
-                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    a.record(stream)
-                    fn()
-                    b.record(stream)
-                    ev[name].append((a, b))
-                else:
-                    fn()
-            Md = M.detach()
-            timed("weight_radon", lambda: P.dc_weight_radon(plan, g, R))
-            timed("filter", lambda: P.dc_filter(plan, R, Md, H))
-            timed("detector_bp", lambda: P.dc_detector_bp(plan, H, gF))
-            timed("cone_bp", lambda: P.dc_cone_bp(plan, gF, f, relu=True))
-            diff = f - target
-            loss_box["loss"] = (diff * diff).mean()
-            Gf = diff * (2.0 / nvox)
-            timed("cone_bp_adjoint", lambda: P.dc_cone_bp_adjoint(plan, Gf, GgF, f_relu=f))
-            timed("detector_bp_adjoint", lambda: P.dc_detector_bp_adjoint(plan, GgF, GH))
-            timed("filter_adjoint", lambda: P.dc_filter_adjoint(plan, GH, R, Md, GM=GM))
-            M.grad = GM
-            opt.step()
-
-        for _ in range(args.warmup):
-            run(False)
-        torch.cuda.synchronize()
-        log(store, "warmup done, loss", float(loss_box["loss"]) if loss_box else None)
-        t0 = time.perf_counter()
-        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        for _ in range(args.steps):
-            run(True)
-        end.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = start.elapsed_time(end) / args.steps
-        kern = {s: sum(a.elapsed_time(b) for a, b in ev[s]) / len(ev[s]) for s in stages}
-        log(store, "ms/step %.2f (wall %.2f)" % (ms, 1e3 * wall / args.steps), json.dumps(kern))
-        work = stage_work(grid, V, bpe)
+        tr = Trainer(P, plan, g, target, sdt)
+        ms, kern = time_eager([tr], args.steps, args.warmup, per_stage=True)
+        log(store, "ms/step %.2f" % ms, json.dumps(kern), "rel error %.5f" % tr.rel_error())
+        work = stage_work(grid, V, 4 if store == "f32" else 2)
         per_kernel = {}
-        for s in stages:
-            units, byts = work[s]
-            t = kern[s] * 1e-3
-            per_kernel[s] = {"ms": round(kern[s], 3), "GB/s": round(byts / t / 1e9, 1),
-                             "TFLOP/s": round(units * FLOPS_PER_UNIT[s] / t / 1e12, 2),
-                             "units_per_s": units / t}
-        results[store] = dict(ms=ms, kern=kern, per_kernel=per_kernel, work=work,
-                              loss=float(loss_box["loss"]))
-        del R, H, gF, f, GgF, GH, M, GM, opt
+        for st in Trainer.STAGES:
+            units, byts = work[st]
+            t = kern[st] * 1e-3
+            per_kernel[st] = {"ms": round(kern[st], 3), "GB/s": round(byts / t / 1e9, 1),
+                              "TFLOP/s": round(units * FLOPS_PER_UNIT[st] / t / 1e12, 2),
+                              "units_per_s": units / t}
+        results[store] = dict(ms=ms, kern=kern, per_kernel=per_kernel, work=work, rel_error=tr.rel_error())
+        del tr
+        torch.cuda.empty_cache()
+    graph_ms = None
+    if args.dtype != "f32":
+        tr = Trainer(P, plan, g, target, torch.bfloat16)
+        graph_ms, _graph = time_graph(tr, args.steps, args.warmup)
+        log("bf16 graph ms/step %.2f" % graph_ms)
+        del tr, _graph
         torch.cuda.empty_cache()
 
     main_store = "f32" if "f32" in results else "bf16"
@@ -258,11 +370,20 @@ def main():
                    "volume": [grid.nz, grid.ny, grid.nx]},
         "roofline": roof,
         "kernels": r["per_kernel"],
+        "rel_error": round(r["rel_error"], 6),
     }
     if "bf16" in results and main_store == "f32":
         b = results["bf16"]
         out["bf16"] = {"value": nvox * V / (b["ms"] * 1e-3), "ms_per_step": round(b["ms"], 3),
-                       "kernels": b["per_kernel"], "speedup_vs_f32": round(r["ms"] / b["ms"], 3)}
+                       "kernels": b["per_kernel"], "speedup_vs_f32": round(r["ms"] / b["ms"], 3),
+                       "rel_error": round(b["rel_error"], 6)}
+    if graph_ms is not None:
+        out["bf16_graph"] = {"value": nvox * V / (graph_ms * 1e-3), "ms_per_step": round(graph_ms, 3),
+                             "speedup_vs_f32": round(r["ms"] / graph_ms, 3) if main_store == "f32" else None}
+    if not args.no_batched:
+        del plan
+        torch.cuda.empty_cache()
+        out["batched"] = batched_c4(P, synth, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(grid, views, args.cpu_views)

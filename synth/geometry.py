@@ -242,3 +242,25 @@ def config_geometry(name: str, n_views: int | None = None):
     else:
         raise ValueError(c["orbit"])
     return grid, views
+
+
+# Batched training workload: 8 scans on the C2 grid with mixed orbits and view
+# counts from 248 to 496 (3002 views), one phantom seed each.
+C4_MIX = [("circle", 248), ("sinusoid", 496), ("circle_arc", (100, 360)), ("circle", 496),
+          ("sinusoid", 248), ("circle_arc", (60, 250)), ("circle", 372), ("sinusoid", 372)]
+C4_SEEDS = list(range(40, 48))
+
+
+def c4_scans():
+    """(Grid, [Views per scan], [phantom seed per scan]) of the batched workload."""
+    c = CONFIGS["C2"]
+    grid, _ = config_geometry("C2", n_views=4)
+    sets = []
+    for kind, n in C4_MIX:
+        if kind == "circle":
+            sets.append(circle_orbit(n, c["sid"], c["sdd"]))
+        elif kind == "sinusoid":
+            sets.append(sinusoid_orbit(n, c["sid"], c["sdd"], c["amp_mm"], c["periods"]))
+        else:
+            sets.append(circle_arc_orbit(n[0], n[1], c["sid"], c["sdd"], 30.0))
+    return grid, sets, list(C4_SEEDS)
