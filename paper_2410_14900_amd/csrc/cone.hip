@@ -74,7 +74,9 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
   const double den = fma(x, P[0], fma(y, P[1], fma(z, P[2], P[3])));
   const double nu = fma(x, P[4], fma(y, P[5], fma(z, P[6], P[7])));
   const double nv = fma(x, P[8], fma(y, P[9], fma(z, P[10], P[11])));
-  float iu = (float)(nu / den), jv = (float)(nv / den);
+  // a float reciprocal is ample here: its error (~1e-4 pixel) is far inside the box margin
+  const float rd = __builtin_amdgcn_rcpf((float)den);
+  float iu = (float)nu * rd, jv = (float)nv * rd;
   float imin = iu, imax = iu, jmin = jv, jmax = jv;
 #pragma unroll
   for (int m = 1; m < 8; m <<= 1) {
@@ -167,9 +169,25 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
         if (e < b.w * b.h) tile[buf][e] = to_f32(stg[s]);
       }
     };
+    // Footprints are computed by one wave per view, two views ahead, and passed
+    // on in a two-slot LDS ring: the box of view v sits in slot (v - v0) & 1 from
+    // the barrier that ends iteration v - 2 until all threads have read it at the
+    // start of iteration v - 1, after which the slot takes the box of view v + 2.
+    __shared__ int4 sBox[2];
+    const int wave = tid >> 6;
+    auto publish = [&](int v, int slot) {
+      const Box b = block_footprint(proj + 12 * v, bx0, bx1, by0, by1, bz0, bz1);
+      if ((tid & 63) == 0) sBox[slot] = make_int4(b.i_lo, b.j_lo, b.w, b.h);
+    };
+    auto box_of = [&](int slot) {
+      const int4 b = sBox[slot];
+      return Box{b.x, b.y, b.z, b.w};
+    };
     Box cur{0, 0, 0, 0};
     if (nv > 0) {
-      cur = block_footprint(proj + 12 * v0, bx0, bx1, by0, by1, bz0, bz1);
+      if (wave < 2 && wave < nv) publish(v0 + wave, wave);
+      __syncthreads();
+      cur = box_of(0);
       load_stage(v0, cur);
       store_stage(0, cur);
     }
@@ -179,13 +197,17 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
       Box nxt{0, 0, 0, 0};
       const bool more = v + 1 < v0 + nv;
       if (more) {
-        nxt = block_footprint(proj + 12 * (v + 1), bx0, bx1, by0, by1, bz0, bz1);
+        nxt = box_of(buf ^ 1);
         load_stage(v + 1, nxt);
       }
+      if (v + 2 < v0 + nv && wave == ((v - v0) & 3)) publish(v + 2, buf);
       const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
       const float* t = tile[buf];
+      // Tap indices need no clamping: every voxel of the block projects inside the
+      // convex hull of its corners' projections, and the staged box extends that
+      // hull by at least one pixel on each side (float rounding of the corners and
+      // of the per-voxel walk is below 1e-4 pixel).
       const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
-      const int wm = cur.w - 2, hm = cur.h - 2;
 #pragma unroll
       for (int z = 0; z < kZC; ++z) {
         const float den = fmaf((float)z, c.dden, c.den);
@@ -194,7 +216,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
         const float w = fmaf((float)z, c.ldv, c.lv) * r;
         const float fu0 = floorf(u), fw0 = floorf(w);
         const float fu = u - fu0, fw = w - fw0;
-        const int i = min(max(oi + (int)fu0, 0), wm), j = min(max(oj + (int)fw0, 0), hm);
+        const int i = oi + (int)fu0, j = oj + (int)fw0;
         const int q = j * cur.w + i;
         const float a00 = t[q], a01 = t[q + 1], a10 = t[q + cur.w], a11 = t[q + cur.w + 1];
         const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
