@@ -50,7 +50,7 @@ def smooth_weights(M, sigma, radius):
     M = np.asarray(M, np.float64)
     Smu = pass_matrix(M.shape[1], sigma, radius)
     Ss = pass_matrix(M.shape[2], sigma, radius)
-    return np.einsum("ka,vab,mb->vkm", Smu, M, Ss)
+    return np.matmul(np.matmul(Smu, M), Ss.T)
 
 
 def smooth_weights_adjoint(G, sigma, radius):
@@ -58,4 +58,4 @@ def smooth_weights_adjoint(G, sigma, radius):
     G = np.asarray(G, np.float64)
     Smu = pass_matrix(G.shape[1], sigma, radius)
     Ss = pass_matrix(G.shape[2], sigma, radius)
-    return np.einsum("ak,vab,bm->vkm", Smu, G, Ss)
+    return np.matmul(np.matmul(Smu.T, G), Ss)
