@@ -161,6 +161,20 @@ dc_status dc_cone_bp(dc_plan plan, const void* gF, dc_dtype tF, float* f, int32_
 dc_status dc_cone_bp_adjoint(dc_plan plan, const float* Gf, const float* f_relu, void* GgF,
                              dc_dtype tF, int32_t v0, int32_t nv, hipStream_t stream);
 
+/* The Gaussian filter layer after the weight layer (Sec. 3.1; the paper uses
+ * sigma = 20, 121 taps): Ms = G_mu G_s M per view, the separable 2D Gaussian over
+ * the (mu, s) grid with taps exp(-t^2 / (2 sigma^2)) normalised over
+ * t = -radius..radius and mirror padding (the edge sample is not repeated) along
+ * both axes; views are not mixed.  M, Ms float32 [V][n_theta][n_s]; Ms may alias M.
+ * Needs sigma > 0, 1 <= radius <= 255, radius < n_theta and radius < n_s
+ * (DC_EINVAL / DC_ESHAPE otherwise) and n_theta + 2 radius <= 1024 (DC_ENOTSUP). */
+dc_status dc_smooth_weights(dc_plan plan, const float* M, float* Ms, double sigma, int32_t radius,
+                            int32_t v0, int32_t nv, hipStream_t stream);
+/* Exact transpose of dc_smooth_weights: GM = G_s^T G_mu^T GMs (the backward of the
+ * layer).  GM float32, overwritten; GM may alias GMs.  Same limits. */
+dc_status dc_smooth_weights_adjoint(dc_plan plan, const float* GMs, float* GM, double sigma, int32_t radius,
+                                    int32_t v0, int32_t nv, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

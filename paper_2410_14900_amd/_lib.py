@@ -60,6 +60,8 @@ SIGNATURES = {
     "dc_detector_bp_adjoint": (_i, [_p, _vp, _i, _vp, _i, _i, _i, _vp]),
     "dc_cone_bp": (_i, [_p, _vp, _i, _vp, _i, _i, _i, _i, _vp]),
     "dc_cone_bp_adjoint": (_i, [_p, _vp, _vp, _vp, _i, _i, _i, _vp]),
+    "dc_smooth_weights": (_i, [_p, _vp, _vp, c_double, _i, _i, _i, _vp]),
+    "dc_smooth_weights_adjoint": (_i, [_p, _vp, _vp, c_double, _i, _i, _i, _vp]),
 }
 
 _LIB = None

@@ -516,4 +516,37 @@ dc_status dc_cone_bp_adjoint(dc_plan plan, const float* Gf, const float* f_relu,
   return launched(launch_cone_fp(p, Gf, f_relu, GgF, tF, v0, nv, stream), "dc_cone_bp_adjoint");
 }
 
+static dc_status check_smooth(const Plan& p, double sigma, int32_t radius) {
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(DC_EINVAL, "sigma must be positive and finite");
+  if (radius < 1 || radius > kSmoothMaxRadius)
+    return fail(DC_EINVAL, "radius must be in [1, " + std::to_string(kSmoothMaxRadius) + "]");
+  if (radius >= p.grid.n_theta || radius >= p.grid.n_s)
+    return fail(DC_ESHAPE, "radius must be below n_theta and n_s (mirror padding)");
+  if (p.grid.n_theta + 2 * radius > 1024)
+    return fail(DC_ENOTSUP, "n_theta + 2 radius above 1024 (the mu pass stages a column block in LDS)");
+  return DC_OK;
+}
+
+dc_status dc_smooth_weights(dc_plan plan, const float* M, float* Ms, double sigma, int32_t radius, int32_t v0,
+                            int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(M, "M"));
+  DC_TRY(check_ptr(Ms, "Ms"));
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  DC_TRY(check_smooth(p, sigma, radius));
+  if (nv == 0) return DC_OK;
+  return launched(launch_smooth(p, M, Ms, sigma, radius, false, v0, nv, stream), "dc_smooth_weights");
+}
+
+dc_status dc_smooth_weights_adjoint(dc_plan plan, const float* GMs, float* GM, double sigma, int32_t radius,
+                                    int32_t v0, int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(GMs, "GMs"));
+  DC_TRY(check_ptr(GM, "GM"));
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  DC_TRY(check_smooth(p, sigma, radius));
+  if (nv == 0) return DC_OK;
+  return launched(launch_smooth(p, GMs, GM, sigma, radius, true, v0, nv, stream), "dc_smooth_weights_adjoint");
+}
+
 }  // extern "C"

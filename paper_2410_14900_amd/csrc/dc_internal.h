@@ -98,6 +98,15 @@ int interp_tile(int axis);
 // sample holding view v0 (the last one when v0 = V)
 void sample_span(const Plan& p, int v0, int nv, int* s_lo, int* s_hi);
 
+// Gaussian weight smoothing (smooth.hip): normalised taps w[|t|], t = -r..r
+static constexpr int kSmoothMaxRadius = 255;
+struct GaussTaps {
+  float w[kSmoothMaxRadius + 1];
+};
+GaussTaps gauss_taps(double sigma, int r);
+hipError_t launch_smooth(const Plan& p, const float* in, float* out, double sigma, int r, bool adjoint, int v0,
+                         int nv, hipStream_t s);
+
 // scratch helpers (radon2d.hip)
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 

@@ -207,3 +207,25 @@ def dc_cone_bp_adjoint(plan, Gf, GgF, f_relu=None, v0=0, nv=None, stream=None):
     check(_lib.lib().dc_cone_bp_adjoint(plan.handle, _ptr(Gf), _ptr(f_relu), _ptr(GgF), _DT[GgF.dtype], v0, nv,
                                         _stream(stream)), "dc_cone_bp_adjoint")
     return GgF
+
+
+def dc_smooth_weights(plan, M, Ms, sigma=20.0, radius=60, v0=0, nv=None, stream=None):
+    """Gaussian filter layer on the weight (Ms may be M itself)."""
+    V = plan.n_views
+    _need(M, "M", (V,) + plan.sino_shape)
+    _need(Ms, "Ms", (V,) + plan.sino_shape)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_smooth_weights(plan.handle, _ptr(M), _ptr(Ms), float(sigma), int(radius), v0, nv,
+                                       _stream(stream)), "dc_smooth_weights")
+    return Ms
+
+
+def dc_smooth_weights_adjoint(plan, GMs, GM, sigma=20.0, radius=60, v0=0, nv=None, stream=None):
+    """Transpose of dc_smooth_weights (GM may be GMs itself)."""
+    V = plan.n_views
+    _need(GMs, "GMs", (V,) + plan.sino_shape)
+    _need(GM, "GM", (V,) + plan.sino_shape)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_smooth_weights_adjoint(plan.handle, _ptr(GMs), _ptr(GM), float(sigma), int(radius), v0,
+                                               nv, _stream(stream)), "dc_smooth_weights_adjoint")
+    return GM

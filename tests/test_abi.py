@@ -84,3 +84,4 @@ def test_batched_plan_rejects_more_samples_than_the_backprojection_grid_holds(P)
     views = synth.sinusoid_orbit(520, 750.0, 1200.0)
     with pytest.raises(P.DcError, match="DC_ENOTSUP"):
         P.Plan(g, views, first_view=first)
+

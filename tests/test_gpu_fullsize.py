@@ -10,6 +10,7 @@ import pytest
 
 import synth
 from oracle import pipeline as O
+from oracle import smooth as OS
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -186,3 +187,19 @@ def test_full_adjoint_pairings(c2):
     pairs.append((inner(Ax, y), inner(x, Aty)))
     for (lhs, n1), (rhs, n2) in pairs:
         assert abs(lhs - rhs) <= 1e-6 * max(n1, n2), (lhs, rhs, n1, n2)
+
+
+def test_full_smooth_weights_paper_filter(c2):
+    """The paper's Gaussian layer (sigma 20, 121 taps) over all 496 views."""
+    P, g, views, plan = c2
+    V = len(views)
+    M = urand((V, g.n_theta, g.n_s), 40, -1.0, 0.0)
+    Ms = torch.empty_like(M)
+    P.dc_smooth_weights(plan, M, Ms, 20.0, 60)
+    ref = OS.smooth_weights(host(M[SAMPLE_VIEWS]), 20.0, 60)
+    assert max(per_view(Ms, ref)) < TOL32
+    G = urand((V, g.n_theta, g.n_s), 41)
+    GM = torch.empty_like(G)
+    P.dc_smooth_weights_adjoint(plan, G, GM, 20.0, 60)
+    ref = OS.smooth_weights_adjoint(host(G[SAMPLE_VIEWS]), 20.0, 60)
+    assert max(per_view(GM, ref)) < TOL32

@@ -109,3 +109,14 @@ def test_one_above_each_limit_is_rejected(P):
     g, views = deep_volume()
     with pytest.raises(P.DcError, match="DC_ESHAPE"):
         P.Plan(dataclasses.replace(g, nz=1025), views)
+
+
+def test_smoothing_arguments_are_checked_on_the_host(P):
+    """The smoothing calls reject bad sigma / radius before any launch."""
+    g, v = synth.config_geometry("C1", n_views=4)
+    plan = P.Plan(g, v)
+    M = torch.zeros((4, g.n_theta, g.n_s), device="cuda")
+    for sigma, radius, status in [(0.0, 5, "DC_EINVAL"), (2.0, 0, "DC_EINVAL"), (2.0, 256, "DC_EINVAL"),
+                                  (2.0, g.n_s, "DC_ESHAPE")]:
+        with pytest.raises(P.DcError, match=status):
+            P.dc_smooth_weights(plan, M, M, sigma, radius)

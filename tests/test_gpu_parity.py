@@ -12,6 +12,7 @@ import pytest
 
 import synth
 from oracle import pipeline as O
+from oracle import smooth as OS
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -164,6 +165,38 @@ def test_cone_bp_adjoint(P, case):
     assert rel(host(GgF), O.cone_bp_adjoint(Gf.astype(np.float64), g, views)) < TOL32
     P.dc_cone_bp_adjoint(plan, dev(Gf), GgF, f_relu=dev(fr))
     assert rel(host(GgF), O.cone_bp_adjoint(Gf.astype(np.float64), g, views, relu_f=fr)) < TOL32
+
+
+# ---------------------------------------------- Gaussian weight smoothing
+def smooth_params(g):
+    """The paper's sigma 20 / 121 taps where the angle grid allows it, else scaled down."""
+    sigma = 20.0 if g.n_theta > 120 else g.n_theta / 8.0
+    return sigma, min(60, int(3 * sigma), g.n_theta - 1, g.n_s - 1)
+
+
+def test_smooth_weights_and_transpose(P, case):
+    name, g, views, plan = case
+    V = len(views)
+    sigma, radius = smooth_params(g)
+    M = rnd((V, g.n_theta, g.n_s), 20, -1.0, 0.0)
+    Ms = torch.empty((V, g.n_theta, g.n_s), device="cuda")
+    P.dc_smooth_weights(plan, dev(M), Ms, sigma, radius)
+    assert rel(host(Ms), OS.smooth_weights(M.astype(np.float64), sigma, radius)) < TOL32
+    G = rnd((V, g.n_theta, g.n_s), 21)
+    GM = torch.empty_like(Ms)
+    P.dc_smooth_weights_adjoint(plan, dev(G), GM, sigma, radius)
+    assert rel(host(GM), OS.smooth_weights_adjoint(G.astype(np.float64), sigma, radius)) < TOL32
+    # in place gives the same bits
+    X = dev(M)
+    P.dc_smooth_weights(plan, X, X, sigma, radius)
+    assert torch.equal(X, Ms)
+    Y = dev(G)
+    P.dc_smooth_weights_adjoint(plan, Y, Y, sigma, radius)
+    assert torch.equal(Y, GM)
+    # adjoint identity on the GPU
+    lhs = float((Ms.double() * dev(G).double()).sum())
+    rhs = float((dev(M).double() * GM.double()).sum())
+    assert abs(lhs - rhs) <= 1e-6 * float(Ms.double().norm() * dev(G).double().norm())
 
 
 # ------------------------------------------------------ adjoint identities
