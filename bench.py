@@ -125,8 +125,9 @@ class Trainer:
 
     STAGES = ["weight_radon", "filter", "detector_bp", "cone_bp", "cone_bp_adjoint", "detector_bp_adjoint",
               "filter_adjoint"]
+    SMOOTH_STAGES = ["smooth", "smooth_adjoint"]
 
-    def __init__(self, P, plan, g, target, store):
+    def __init__(self, P, plan, g, target, store, smooth=None):
         import torch
         self.P, self.plan, self.g, self.target = P, plan, g, target
         V, (K, S), det = plan.n_views, plan.sino_shape, plan.det_shape
@@ -143,20 +144,27 @@ class Trainer:
         self.m, self.v = torch.zeros_like(self.M), torch.zeros_like(self.M)
         self.t = torch.zeros((), device=dev)
         self.gscale = 2.0 / target.numel()
+        # the Gaussian filter layer on the weight (sigma, radius), applied before use
+        self.smooth = smooth
+        self.Mw = torch.empty_like(self.M) if smooth else self.M
 
     def step(self, timed=None):
         import torch
         P, pl = self.P, self.plan
         run = timed or (lambda name, fn: fn())
         run("weight_radon", lambda: P.dc_weight_radon(pl, self.g, self.R))
-        run("filter", lambda: P.dc_filter(pl, self.R, self.M, self.H))
+        if self.smooth:
+            run("smooth", lambda: P.dc_smooth_weights(pl, self.M, self.Mw, *self.smooth))
+        run("filter", lambda: P.dc_filter(pl, self.R, self.Mw, self.H))
         run("detector_bp", lambda: P.dc_detector_bp(pl, self.H, self.gF))
         run("cone_bp", lambda: P.dc_cone_bp(pl, self.gF, self.f, relu=True))
         torch.sub(self.f, self.target, out=self.Gf)
         self.Gf.mul_(self.gscale)
         run("cone_bp_adjoint", lambda: P.dc_cone_bp_adjoint(pl, self.Gf, self.GgF, f_relu=self.f))
         run("detector_bp_adjoint", lambda: P.dc_detector_bp_adjoint(pl, self.GgF, self.GH))
-        run("filter_adjoint", lambda: P.dc_filter_adjoint(pl, self.GH, self.R, self.M, GM=self.GM))
+        run("filter_adjoint", lambda: P.dc_filter_adjoint(pl, self.GH, self.R, self.Mw, GM=self.GM))
+        if self.smooth:
+            run("smooth_adjoint", lambda: P.dc_smooth_weights_adjoint(pl, self.GM, self.GM, *self.smooth))
         adam_(self.M, self.GM, self.m, self.v, self.t)
 
     def rel_error(self):
@@ -169,7 +177,7 @@ def time_eager(trainers, steps, warmup, per_stage=False):
     """ms per step of running every trainer's step once, eagerly; optional per-stage event times."""
     import torch
     stream = torch.cuda.current_stream()
-    ev = {s: [] for s in Trainer.STAGES}
+    ev = {s: [] for s in Trainer.STAGES + Trainer.SMOOTH_STAGES}
 
     def timed(name, fn):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -190,7 +198,8 @@ def time_eager(trainers, steps, warmup, per_stage=False):
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / steps
-    kern = {s: sum(a.elapsed_time(b) for a, b in ev[s]) / len(ev[s]) for s in Trainer.STAGES} if per_stage else None
+    kern = ({s: sum(a.elapsed_time(b) for a, b in ev[s]) / len(ev[s]) for s in ev if ev[s]}
+            if per_stage else None)
     return ms, kern
 
 
@@ -330,6 +339,15 @@ def main():
         results[store] = dict(ms=ms, kern=kern, per_kernel=per_kernel, work=work, rel_error=tr.rel_error())
         del tr
         torch.cuda.empty_cache()
+    # the step with the paper's Gaussian filter layer on the weight (sigma 20, 121 taps)
+    tr = Trainer(P, plan, g, target, torch.float32, smooth=(20.0, 60))
+    sm_ms, sm_kern = time_eager([tr], args.steps, args.warmup, per_stage=True)
+    smoothing = {"ms_per_step": round(sm_ms, 3), "smooth_ms": round(sm_kern["smooth"], 3),
+                 "smooth_adjoint_ms": round(sm_kern["smooth_adjoint"], 3), "sigma": 20.0, "taps": 121,
+                 "rel_error": round(tr.rel_error(), 6)}
+    log("f32 with the Gaussian weight layer: ms/step %.2f" % sm_ms, json.dumps(smoothing))
+    del tr
+    torch.cuda.empty_cache()
     graph_ms = None
     if args.dtype != "f32":
         tr = Trainer(P, plan, g, target, torch.bfloat16)
@@ -377,6 +395,7 @@ def main():
         out["bf16"] = {"value": nvox * V / (b["ms"] * 1e-3), "ms_per_step": round(b["ms"], 3),
                        "kernels": b["per_kernel"], "speedup_vs_f32": round(r["ms"] / b["ms"], 3),
                        "rel_error": round(b["rel_error"], 6)}
+    out["with_weight_smoothing"] = smoothing
     if graph_ms is not None:
         out["bf16_graph"] = {"value": nvox * V / (graph_ms * 1e-3), "ms_per_step": round(graph_ms, 3),
                              "speedup_vs_f32": round(r["ms"] / graph_ms, 3) if main_store == "f32" else None}

@@ -20,21 +20,25 @@ def sinogram(plan, g, dtype=torch.float32, out=None):
 
 class _DCFBP(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, M, R, g, plan, mode, store_dtype, relu, recompute_R):
+    def forward(ctx, M, R, g, plan, mode, store_dtype, relu, recompute_R, smooth):
         V = plan.n_views
         dev = M.device
         if R is None:
             R = sinogram(plan, g)
+        Mw = M
+        if smooth is not None:
+            Mw = ops.dc_smooth_weights(plan, M, torch.empty_like(M), *smooth)
         H = torch.empty((V,) + plan.sino_shape, device=dev, dtype=store_dtype)
-        ops.dc_filter(plan, R, M, H, mode=mode)
+        ops.dc_filter(plan, R, Mw, H, mode=mode)
         gF = torch.empty((V,) + plan.det_shape, device=dev, dtype=store_dtype)
         ops.dc_detector_bp(plan, H, gF)
         del H
         f = torch.empty(plan.vol_shape, device=dev, dtype=torch.float32)
         ops.dc_cone_bp(plan, gF, f, relu=relu)
         ctx.plan, ctx.mode, ctx.store_dtype, ctx.relu, ctx.recompute_R = plan, mode, store_dtype, relu, recompute_R
+        ctx.smooth = smooth
         saved_R = None if recompute_R else R
-        ctx.save_for_backward(M, saved_R, g if recompute_R else None, f if relu else None)
+        ctx.save_for_backward(Mw, saved_R, g if recompute_R else None, f if relu else None)
         return f
 
     @staticmethod
@@ -52,15 +56,20 @@ class _DCFBP(torch.autograd.Function):
         del GgF
         GM = torch.empty_like(M)
         ops.dc_filter_adjoint(plan, GH, R, M, GM=GM, mode=ctx.mode)
-        return GM, None, None, None, None, None, None, None
+        if ctx.smooth is not None:
+            ops.dc_smooth_weights_adjoint(plan, GM, GM, *ctx.smooth)
+        return GM, None, None, None, None, None, None, None, None
 
 
 def reconstruct(plan, M, g=None, R=None, mode="analytic", store_dtype=torch.float32, relu=False,
-                recompute_R=False):
+                recompute_R=False, smooth=None):
     """f = DC-FBP(g; M).  Pass the sinogram R (from ``sinogram``) to reuse it
-    across steps, or g to compute it; recompute_R keeps only g for the backward."""
+    across steps, or g to compute it; recompute_R keeps only g for the backward.
+    smooth = (sigma, radius) inserts the Gaussian filter layer on M (Sec. 3.1:
+    (20.0, 60)) before the weight is used; its transpose runs in the backward."""
     if R is None and g is None:
         raise ValueError("need g or R")
     if recompute_R and g is None:
         raise ValueError("recompute_R needs g")
-    return _DCFBP.apply(M, R, g, plan, mode, store_dtype, relu, recompute_R)
+    return _DCFBP.apply(M, R, g, plan, mode, store_dtype, relu, recompute_R,
+                        None if smooth is None else (float(smooth[0]), int(smooth[1])))

@@ -266,6 +266,25 @@ def test_gradient_wrt_M(P, case):
     assert rel(host(Mt.grad), ref) < TOL_GRAD
 
 
+def test_gradient_wrt_M_through_the_smoothing_layer(P, case):
+    """f = DC-FBP(g; G M) with the Gaussian layer G: dL/dM = G^T dL/dW at W = G M."""
+    name, g, views, plan = case
+    V = len(views)
+    sigma, radius = smooth_params(g)
+    gp, _ = _projections(g, views)
+    rng = np.random.Generator(np.random.PCG64(5))
+    M = rng.uniform(0.3, 0.7, (V, g.n_theta, g.n_s)).astype(np.float32)
+    target = rng.uniform(0, 1e-3, (g.nz, g.ny, g.nx)).astype(np.float32)
+    Mt = dev(M).requires_grad_(True)
+    f = P.reconstruct(plan, Mt, g=dev(gp), smooth=(sigma, radius))
+    (0.5 * ((f - dev(target)) ** 2).sum()).backward()
+    W = OS.smooth_weights(M.astype(np.float64), sigma, radius)
+    fo = O.reconstruct(gp.astype(np.float64), W, g, views)
+    assert rel(host(f), fo) < TOL32
+    ref = OS.smooth_weights_adjoint(O.grad_M(gp.astype(np.float64), W, fo - target, g, views), sigma, radius)
+    assert rel(host(Mt.grad), ref) < TOL_GRAD
+
+
 @pytest.mark.parametrize("store", ["f32", "bf16"])
 def test_forward_backward_bit_reproducible(P, case, store):
     """Two runs of the whole chain (forward, ReLU, backward to dL/dM) give identical bits."""
