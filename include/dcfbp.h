@@ -175,6 +175,18 @@ dc_status dc_smooth_weights(dc_plan plan, const float* M, float* Ms, double sigm
 dc_status dc_smooth_weights_adjoint(dc_plan plan, const float* GMs, float* GM, double sigma, int32_t radius,
                                     int32_t v0, int32_t nv, hipStream_t stream);
 
+/* The structural term of the training loss (eq. 13), read as the standard 3D SSIM:
+ * Gaussian window of standard deviation 1.5 and 11 taps per axis, C1 = (0.01 L)^2,
+ * C2 = (0.03 L)^2 with L = data_range, mean over the positions where the whole
+ * window lies inside the volume.  x, y float32 [nz][ny][nx], every side >= 11.
+ * *ssim (one float on the device) receives the mean; grad_x (nullable) receives
+ * d SSIM / d x, overwritten.  work: device buffer of at least
+ * dc_ssim_workspace_bytes(nz, ny, nx) bytes owned by the caller; the mean is
+ * reduced in a fixed order, so results are bit-reproducible.  Not tied to a plan. */
+size_t dc_ssim_workspace_bytes(int32_t nz, int32_t ny, int32_t nx);
+dc_status dc_ssim(const float* x, const float* y, int32_t nz, int32_t ny, int32_t nx, float data_range,
+                  float* ssim, float* grad_x, void* work, size_t work_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

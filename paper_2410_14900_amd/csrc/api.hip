@@ -549,4 +549,24 @@ dc_status dc_smooth_weights_adjoint(dc_plan plan, const float* GMs, float* GM, d
   return launched(launch_smooth(p, GMs, GM, sigma, radius, true, v0, nv, stream), "dc_smooth_weights_adjoint");
 }
 
+size_t dc_ssim_workspace_bytes(int32_t nz, int32_t ny, int32_t nx) {
+  if (nz < 11 || ny < 11 || nx < 11) return 0;
+  return ssim_workspace_bytes(nz, ny, nx);
+}
+
+dc_status dc_ssim(const float* x, const float* y, int32_t nz, int32_t ny, int32_t nx, float data_range,
+                  float* ssim, float* grad_x, void* work, size_t work_bytes, hipStream_t stream) {
+  if (nz < 11 || ny < 11 || nx < 11) return fail(DC_ESHAPE, "every volume side must be at least 11 (the window)");
+  if ((double)nz * ny * nx > 2147483647.0) return fail(DC_ESHAPE, "volume too large");
+  if (!(data_range > 0.f) || !std::isfinite(data_range)) return fail(DC_EINVAL, "data_range must be positive");
+  DC_TRY(check_ptr(x, "x"));
+  DC_TRY(check_ptr(y, "y"));
+  DC_TRY(check_ptr(ssim, "ssim"));
+  DC_TRY(check_ptr(grad_x, "grad_x", true));
+  DC_TRY(check_ptr(work, "work"));
+  if (work_bytes < ssim_workspace_bytes(nz, ny, nx))
+    return fail(DC_ESHAPE, "workspace smaller than dc_ssim_workspace_bytes()");
+  return launched(launch_ssim(x, y, nz, ny, nx, data_range, ssim, grad_x, work, stream), "dc_ssim");
+}
+
 }  // extern "C"

@@ -107,6 +107,11 @@ GaussTaps gauss_taps(double sigma, int r);
 hipError_t launch_smooth(const Plan& p, const float* in, float* out, double sigma, int r, bool adjoint, int v0,
                          int nv, hipStream_t s);
 
+// 3D SSIM and its gradient (ssim.hip)
+size_t ssim_workspace_bytes(int nz, int ny, int nx);
+hipError_t launch_ssim(const float* x, const float* y, int nz, int ny, int nx, float L, float* ssim, float* grad,
+                       void* work, hipStream_t s);
+
 // scratch helpers (radon2d.hip)
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 

@@ -229,3 +229,21 @@ def dc_smooth_weights_adjoint(plan, GMs, GM, sigma=20.0, radius=60, v0=0, nv=Non
     check(_lib.lib().dc_smooth_weights_adjoint(plan.handle, _ptr(GMs), _ptr(GM), float(sigma), int(radius), v0,
                                                nv, _stream(stream)), "dc_smooth_weights_adjoint")
     return GM
+
+
+def dc_ssim(x, y, data_range, grad=False, stream=None):
+    """Mean 3D SSIM of x against y (volumes [nz][ny][nx]) and, with grad=True, its
+    gradient w.r.t. x.  Returns (ssim as a 1-element tensor, grad or None)."""
+    if x.dim() != 3 or tuple(x.shape) != tuple(y.shape):
+        raise ValueError("x and y must be volumes of one shape")
+    _need(x, "x", tuple(x.shape))
+    _need(y, "y", tuple(y.shape))
+    nz, ny, nx = x.shape
+    L = _lib.lib()
+    nbytes = L.dc_ssim_workspace_bytes(nz, ny, nx)
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=x.device)
+    out = torch.empty(1, dtype=torch.float32, device=x.device)
+    g = torch.empty_like(x) if grad else None
+    check(L.dc_ssim(_ptr(x), _ptr(y), nz, ny, nx, float(data_range), _ptr(out), _ptr(g), _ptr(work), nbytes,
+                    _stream(stream)), "dc_ssim")
+    return out, g
