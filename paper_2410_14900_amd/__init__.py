@@ -15,6 +15,7 @@ from .ops import (Plan, validate, dc_weight_radon, dc_weight_radon_adjoint, dc_f
                   dc_filter_adjoint, dc_detector_bp, dc_detector_bp_adjoint, dc_cone_bp,
                   dc_cone_bp_adjoint, dc_smooth_weights, dc_smooth_weights_adjoint, dc_ssim)
 from .autograd import reconstruct, sinogram  # noqa: E402
+from . import train  # noqa: E402,F401
 
 __all__ = ["Plan", "validate", "DcError", "header_symbols", "reconstruct", "sinogram",
            "dc_weight_radon", "dc_weight_radon_adjoint", "dc_filter", "dc_filter_adjoint",
