@@ -175,6 +175,14 @@ dc_status dc_smooth_weights(dc_plan plan, const float* M, float* Ms, double sigm
 dc_status dc_smooth_weights_adjoint(dc_plan plan, const float* GMs, float* GM, double sigma, int32_t radius,
                                     int32_t v0, int32_t nv, hipStream_t stream);
 
+/* Projection data from a voxel volume (the paper trains on simulated projections,
+ * Sec. 3.3): g[v](i,j) = Siddon's exact line integral of the piecewise-constant
+ * volume f (value f[z][y][x] on voxel [x-1/2, x+1/2] vx ... around each centre)
+ * along the segment from the source of view v to the centre of pixel (i, j).
+ * vol float32 [nz][ny][nx] ([S][nz][ny][nx] for a batched plan: each view reads its
+ * own sample's volume); g float32 [V][nv][nu], views [v0, v0+nv) overwritten. */
+dc_status dc_project(dc_plan plan, const float* vol, float* g, int32_t v0, int32_t nv, hipStream_t stream);
+
 /* The structural term of the training loss (eq. 13), read as the standard 3D SSIM:
  * Gaussian window of standard deviation 1.5 and 11 taps per axis, C1 = (0.01 L)^2,
  * C2 = (0.03 L)^2 with L = data_range, mean over the positions where the whole

@@ -62,6 +62,7 @@ SIGNATURES = {
     "dc_cone_bp_adjoint": (_i, [_p, _vp, _vp, _vp, _i, _i, _i, _vp]),
     "dc_smooth_weights": (_i, [_p, _vp, _vp, c_double, _i, _i, _i, _vp]),
     "dc_smooth_weights_adjoint": (_i, [_p, _vp, _vp, c_double, _i, _i, _i, _vp]),
+    "dc_project": (_i, [_p, _vp, _vp, _i, _i, _vp]),
     "dc_ssim_workspace_bytes": (c_size_t, [_i, _i, _i]),
     "dc_ssim": (_i, [_vp, _vp, _i, _i, _i, c_float, _vp, _vp, _vp, c_size_t, _vp]),
 }

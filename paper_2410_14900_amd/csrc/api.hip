@@ -185,6 +185,14 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
   p->n_chunks = (int)chunks.size() / 4;
 
   std::vector<float> vf(4 * n), rmax2(n);
+  std::vector<double> frame(12 * n);
+  for (int v = 0; v < n; ++v)
+    for (int c = 0; c < 3; ++c) {
+      frame[12 * v + c] = views[v].src[c];
+      frame[12 * v + 3 + c] = views[v].det_center[c];
+      frame[12 * v + 6 + c] = views[v].ex[c];
+      frame[12 * v + 9 + c] = views[v].ey[c];
+    }
   std::vector<double> proj(12 * n);
   double max_cell_terms = 0.0;
   const double X0[3] = {-0.5 * (g->nx - 1) * g->vx + g->ox, -0.5 * (g->ny - 1) * g->vy + g->oy,
@@ -274,6 +282,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
   if ((e = up((void**)&p->d_ang, ang.data(), ang.size() * sizeof(double))) != hipSuccess ||
       (e = up((void**)&p->d_trig, trig.data(), trig.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_view, vf.data(), vf.size() * sizeof(float))) != hipSuccess ||
+      (e = up((void**)&p->d_frame, frame.data(), frame.size() * sizeof(double))) != hipSuccess ||
       (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
       (e = up((void**)&p->d_rmax2, rmax2.data(), rmax2.size() * sizeof(float))) != hipSuccess ||
       (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess ||
@@ -287,8 +296,8 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
 }
 
 static void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_ang,    p->d_trig,   p->d_view,    p->d_proj,   p->d_rmax2,
-                  p->d_chunks, p->d_first,  p->d_scratch, p->d_masked};
+  void* ptrs[] = {p->d_ang,    p->d_trig,  p->d_view,    p->d_frame,  p->d_proj,
+                  p->d_rmax2,  p->d_chunks, p->d_first, p->d_scratch, p->d_masked};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -547,6 +556,15 @@ dc_status dc_smooth_weights_adjoint(dc_plan plan, const float* GMs, float* GM, d
   DC_TRY(check_smooth(p, sigma, radius));
   if (nv == 0) return DC_OK;
   return launched(launch_smooth(p, GMs, GM, sigma, radius, true, v0, nv, stream), "dc_smooth_weights_adjoint");
+}
+
+dc_status dc_project(dc_plan plan, const float* vol, float* g, int32_t v0, int32_t nv, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(vol, "vol"));
+  DC_TRY(check_ptr(g, "g"));
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  return launched(launch_project(p, vol, g, v0, nv, stream), "dc_project");
 }
 
 size_t dc_ssim_workspace_bytes(int32_t nz, int32_t ny, int32_t nx) {

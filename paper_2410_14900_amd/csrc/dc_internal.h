@@ -59,6 +59,8 @@ struct Plan {
   float* d_trig = nullptr;       // [n_theta][2]  cos mu, sin mu
   // per view (float32): D, t.l_x/(4 pi^2 D), t.l_y/(4 pi^2 D), t.l_z/(4 pi^2 D^2)
   float* d_view = nullptr;       // [V][4]
+  // per view (float64) frame for ray tracing: source, detector centre, l_x, l_y
+  double* d_frame = nullptr;     // [V][12]
   // per view (float64) projective map of voxel indices: rows den, num_u, num_v,
   // each with coefficients of (ix, iy, iz, 1); i* = num_u/den, j* = num_v/den,
   // den = U/D, weight (D/U)^2 = 1/den^2
@@ -106,6 +108,9 @@ struct GaussTaps {
 GaussTaps gauss_taps(double sigma, int r);
 hipError_t launch_smooth(const Plan& p, const float* in, float* out, double sigma, int r, bool adjoint, int v0,
                          int nv, hipStream_t s);
+
+// Siddon cone-beam projector (project.hip)
+hipError_t launch_project(const Plan& p, const float* vol, float* g, int v0, int nv, hipStream_t s);
 
 // 3D SSIM and its gradient (ssim.hip)
 size_t ssim_workspace_bytes(int nz, int ny, int nx);

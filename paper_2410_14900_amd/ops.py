@@ -247,3 +247,12 @@ def dc_ssim(x, y, data_range, grad=False, stream=None):
     check(L.dc_ssim(_ptr(x), _ptr(y), nz, ny, nx, float(data_range), _ptr(out), _ptr(g), _ptr(work), nbytes,
                     _stream(stream)), "dc_ssim")
     return out, g
+
+
+def dc_project(plan, vol, g, v0=0, nv=None, stream=None):
+    """Siddon projections of the voxel volume: g[v] for views [v0, v0+nv)."""
+    _need(vol, "vol", plan.vol_shape)
+    _need(g, "g", (plan.n_views,) + plan.det_shape)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_project(plan.handle, _ptr(vol), _ptr(g), v0, nv, _stream(stream)), "dc_project")
+    return g

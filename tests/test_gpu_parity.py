@@ -57,6 +57,10 @@ CASES = {
     "arc": lambda: (synth.Grid(nu=48, nv=40, du=1.2, dv=1.2, n_theta=50, n_s=synth.radon_bins(48, 40), ds=1.2,
                                nx=30, ny=30, nz=30, vx=1.0, vy=1.0, vz=1.0),
                     synth.circle_arc_orbit(4, 8, 750.0, 1200.0, 30.0)),
+    # the paper's fourth orbit (Sec. 4.4): random nearest-neighbour source positions
+    "random-nn": lambda: (synth.Grid(nu=56, nv=44, du=1.1, dv=1.1, n_theta=41, n_s=synth.radon_bins(56, 44), ds=1.1,
+                                     nx=28, ny=26, nz=24, vx=1.0, vy=1.0, vz=1.0),
+                          synth.random_nn_orbit(9, 750.0, 1200.0, 10.0, 5)),
 }
 
 
