@@ -8,6 +8,8 @@
 // The two are exact transposes of each other for equal scales.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "dc_internal.h"
 
 namespace dc {
@@ -119,67 +121,74 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
   // do not, at the price of some 4-way bank conflicts (measured 13% faster than
   // consecutive lines, stride 4 is slower again).
   const int lane_line = ((threadIdx.x >> 7) << 7) + ((threadIdx.x & 63) << 1) + ((threadIdx.x >> 6) & 1);
-  for (int line = lane_line; line < n_lines; line += blockDim.x) {
-    long long t[kSplatKC];
-#pragma unroll
-    for (int kk = 0; kk < kSplatKC; ++kk) {
-      if (kk < kn) {
-        const double t0 = colmajor ? fma((double)line, sB[kk], sC[kk]) : fma((double)line, sA[kk], sC[kk]);
-        const double fl = floor(t0);
-        t[kk] = ((long long)((int)fl + kk * row + 1) << 32) + (long long)(unsigned)((t0 - fl) * 4294967296.0);
-      } else {
-        t[kk] = 0;
+  // Full chunks (kSplatKC angles, nearly all of them) run a copy of the walk
+  // without the per-angle range checks.
+  auto walk = [&](auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    for (int line = lane_line; line < n_lines; line += blockDim.x) {
+      long long t[kSplatKC];
+  #pragma unroll
+      for (int kk = 0; kk < kSplatKC; ++kk) {
+        if (FULL || kk < kn) {
+          const double t0 = colmajor ? fma((double)line, sB[kk], sC[kk]) : fma((double)line, sA[kk], sC[kk]);
+          const double fl = floor(t0);
+          t[kk] = ((long long)((int)fl + kk * row + 1) << 32) + (long long)(unsigned)((t0 - fl) * 4294967296.0);
+        } else {
+          t[kk] = 0;
+        }
       }
-    }
-    // the next kSplatPre pixels of the line are loaded while the current ones
-    // are deposited, so each wave keeps several loads in flight
-    const Tin* base = colmajor ? im + (size_t)line * g.nu : im + line;
-    const int pitch = colmajor ? 1 : g.nu;
-    Tin xb[kSplatPre];   // raw storage values, converted at use
-#pragma unroll
-    for (int q = 0; q < kSplatPre; ++q) xb[q] = q < n_steps ? base[(size_t)q * pitch] : Tin{};
-    for (int p0 = 0; p0 < n_steps; p0 += kSplatPre) {
-      Tin xc[kSplatPre];
-#pragma unroll
-      for (int q = 0; q < kSplatPre; ++q) xc[q] = xb[q];
-      if (p0 + kSplatPre < n_steps) {
-#pragma unroll
+      // the next kSplatPre pixels of the line are loaded while the current ones
+      // are deposited, so each wave keeps several loads in flight
+      const Tin* base = colmajor ? im + (size_t)line * g.nu : im + line;
+      const int pitch = colmajor ? 1 : g.nu;
+      Tin xb[kSplatPre];   // raw storage values, converted at use
+  #pragma unroll
+      for (int q = 0; q < kSplatPre; ++q) xb[q] = q < n_steps ? base[(size_t)q * pitch] : Tin{};
+      for (int p0 = 0; p0 < n_steps; p0 += kSplatPre) {
+        Tin xc[kSplatPre];
+  #pragma unroll
+        for (int q = 0; q < kSplatPre; ++q) xc[q] = xb[q];
+        if (p0 + kSplatPre < n_steps) {
+  #pragma unroll
+          for (int q = 0; q < kSplatPre; ++q) {
+            const int pn = p0 + kSplatPre + q;
+            xb[q] = pn < n_steps ? base[(size_t)pn * pitch] : Tin{};
+          }
+        }
+  #pragma unroll
         for (int q = 0; q < kSplatPre; ++q) {
-          const int pn = p0 + kSplatPre + q;
-          xb[q] = pn < n_steps ? base[(size_t)pn * pitch] : Tin{};
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kSplatPre; ++q) {
-        const int p = p0 + q;
-        if (p >= n_steps) break;
-        const int i = colmajor ? p : line, j = colmajor ? line : p;
-        float x = to_f32(xc[q]);
-        if (WCOS) {
-          const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-          x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
-        }
-        const float xs = x * S;
-        // Integer rounding without conversion instructions: adding 1.5 * 2^23
-        // leaves round-to-nearest-even(v) in the low mantissa bits for |v| < 2^22.
-        const int qa = (int)(__float_as_uint(xs + kRoundMagic) - kRoundMagicBits);
-        // high word = qb + sign extension of qa, taken from the same trick
-        const unsigned hbias = kRoundMagicBits - (unsigned)(qa >> 31);
-        const float xs2 = xs * 2.3283064365386963e-10f;  // xs * 2^-32
-#pragma unroll
-        for (int kk = 0; kk < kSplatKC; ++kk) {
-          if (kk < kn) {
-            const unsigned idx = (unsigned)(t[kk] >> 32);  // kk * row + m + 1
-            const unsigned lo = (unsigned)t[kk];
-            const unsigned hi = __float_as_uint(fmaf(xs2, (float)lo, kRoundMagic)) - hbias;
-            const unsigned long long word = ((unsigned long long)hi << 32) | (unsigned long long)(unsigned)qa;
-            if (!CHECKED || idx - (unsigned)(kk * row) <= (unsigned)ns) atomicAdd(acc + idx, word);
-            t[kk] += sStep[kk];
+          const int p = p0 + q;
+          if (p >= n_steps) break;
+          const int i = colmajor ? p : line, j = colmajor ? line : p;
+          float x = to_f32(xc[q]);
+          if (WCOS) {
+            const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
+            x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+          }
+          const float xs = x * S;
+          // Integer rounding without conversion instructions: adding 1.5 * 2^23
+          // leaves round-to-nearest-even(v) in the low mantissa bits for |v| < 2^22.
+          const int qa = (int)(__float_as_uint(xs + kRoundMagic) - kRoundMagicBits);
+          // high word = qb + sign extension of qa, taken from the same trick
+          const unsigned hbias = kRoundMagicBits - (unsigned)(qa >> 31);
+          const float xs2 = xs * 2.3283064365386963e-10f;  // xs * 2^-32
+  #pragma unroll
+          for (int kk = 0; kk < kSplatKC; ++kk) {
+            if (FULL || kk < kn) {
+              const unsigned idx = (unsigned)(t[kk] >> 32);  // kk * row + m + 1
+              const unsigned lo = (unsigned)t[kk];
+              const unsigned hi = __float_as_uint(fmaf(xs2, (float)lo, kRoundMagic)) - hbias;
+              const unsigned long long word = ((unsigned long long)hi << 32) | (unsigned long long)(unsigned)qa;
+              if (!CHECKED || idx - (unsigned)(kk * row) <= (unsigned)ns) atomicAdd(acc + idx, word);
+              t[kk] += sStep[kk];
+            }
           }
         }
       }
     }
-  }
+  };
+  if (kn == kSplatKC) walk(std::true_type{});
+  else walk(std::false_type{});
   __syncthreads();
   // decode: word = a + 2^32 b with |a| < 2^31
   Tout* o = out + ((size_t)v * g.n_theta + k0) * ns;
