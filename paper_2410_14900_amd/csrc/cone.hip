@@ -244,9 +244,15 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 
 // ------------------------------------------------------------- transpose
 // Gather form of the transpose, without global atomics: one workgroup owns one
-// 8 x 64 pixel tile of 4 consecutive views and visits every voxel whose bilinear
+// 20 x 64 pixel tile of kFV consecutive views and visits every voxel whose bilinear
 // footprint touches it on any of them (each voxel segment is loaded once and
-// projected on every view), i.e. i* in [i0-1, i1), j* in [j0-1, j1).  In voxel-index space these
+// projected on every view), i.e. i* in [i0-1, i1), j* in [j0-1, j1).  One view per
+// workgroup is fastest at 0.5 mm voxels / 0.6 mm pixels: the frusta of neighbouring
+// views differ by a few voxels at the ends of the rays, so a shared x-run is
+// mostly wasted on each of them, while the segment loads it would share come
+// from L2.  Wider tiles amortise the conservative ends of each x-run (72% of the
+// evaluated voxel-views land in the tile at 20-24 pixels, 50% at 8 x 64 over
+// 4 views).  In voxel-index space these
 // are four half-spaces L_k(x) >= 0 (affine because the projection is
 // projective with a positive denominator).  The voxels are enumerated as
 // x-runs of 16-voxel z-segments: every (z-segment, y) row of the volume is
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
 // the ReLU mask once into the plan's volume buffer) and the per-view bound on
 // (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
 // box can reach the tile's window are scanned.
-static constexpr int kFTI = 8, kFTJ = 64, kFZS = 16, kFROWS = 512;
+static constexpr int kFTI = 20, kFTJ = 64, kFZS = 16, kFROWS = 512;
 static constexpr int kFW = kFTI + 1, kFH = kFTJ + 1;
 
 __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
@@ -317,7 +323,15 @@ __global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf
 
 static constexpr int kFMaxLayers = 64;
 
-static constexpr int kFV = 4;   // consecutive views per workgroup (their frusta nearly coincide)
+static constexpr int kFV = 1;   // consecutive views per workgroup
+
+// S[w] for a runtime w without dynamic register indexing
+__device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
+  float r = S[0];
+#pragma unroll
+  for (int k = 1; k < kFV; ++k) r = w == k ? S[k] : r;
+  return r;
+}
 
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
@@ -490,7 +504,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       for (int z = 0; z < kFZS; ++z) gv[z] = z < nzv ? gv[z] : 0.f;
       for (int w = 0; w < nvw; ++w) {
         const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
-        const float Sw = S[0] * 0.f + (w == 0 ? S[0] : w == 1 ? S[1] : w == 2 ? S[2] : S[3]);
+        const float Sw = pick(S, w);
         unsigned long long* ab = sAB[w];
         unsigned long long* ce = sCE[w];
 #pragma unroll
@@ -529,7 +543,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   auto lo32 = [](unsigned long long w) { return (long long)(int)(unsigned)(w & 0xffffffffull); };
   auto hi32 = [](unsigned long long w, long long lo) { return ((long long)w - lo) >> 32; };
   for (int w = 0; w < nvw; ++w) {
-    const double inv = S[0] * 0.f + (w == 0 ? S[0] : w == 1 ? S[1] : w == 2 ? S[2] : S[3]);
+    const double inv = pick(S, w);
     const double invS = inv > 0.0 ? 1.0 / inv : 0.0;
     const unsigned long long* AB = sAB[w];
     const unsigned long long* CE = sCE[w];

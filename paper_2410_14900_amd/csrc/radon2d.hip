@@ -54,7 +54,9 @@ __global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img
     if (WCOS) {
       const int j = q / g.nu, i = q - j * g.nu;
       const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-      x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+      // hardware rsqrt: the argument is at least D^2, far from the denormal
+      // range that rsqrtf's scaling guards (the splat and its transpose use the same)
+      x *= D * __builtin_amdgcn_rsqf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
     }
     mx = fmaxf(mx, fabsf(x));
   }
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
           float x = to_f32(xc[q]);
           if (WCOS) {
             const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-            x *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+            x *= D * __builtin_amdgcn_rsqf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
           }
           const float xs = x * S;
           // Integer rounding without conversion instructions: adding 1.5 * 2^23
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, To
       float val = scale * acc[h];
       if (WCOS) {
         float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-        val *= D * rsqrtf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+        val *= D * __builtin_amdgcn_rsqf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
       }
       o[j * g.nu + i] = from_f32<Tout>(val);
     }
