@@ -46,8 +46,8 @@ FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 9, "cone_bp": 
 # roofline reports traffic as null until the counters are taken again.
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the kernel sources)
-    ("cone_bp_adjoint", "f32"): (17_522_968_246 + 201_423_598,
-                                 "59881c030f7a33449cdc52cb1c6d1dcb1e0ace791455ddddc13db330be93a297"),
+    ("cone_bp_adjoint", "f32"): (7_444_596_335 + 201_423_582,
+                                 "5561bfd8ab8fe9f5c258bd0dc5f8a03a79194c2840744979b966a5fa6e76feb8"),
 }
 
 
