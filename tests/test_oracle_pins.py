@@ -272,6 +272,33 @@ def test_crofton_partition_of_unity(orbit):
     assert checked == 12
 
 
+def test_crofton_open_circle_counts_only_covered_parameters():
+    """Eq. 9 sums over source positions of the orbit: on a half circle a plane
+    whose second crossing of the full circle lies on the missing half meets the
+    orbit once, so the weight of the view it passes through is 1."""
+    views = synth.circle_orbit(64, 750.0, 1200.0, start=0.0, span=math.pi)
+    orb = crofton.Orbit(views)
+    assert not orb.segs[0]["closed"]
+    seg, tau = orb.locate(32)                       # lambda = pi / 2, mid-segment (taper 1)
+    th = np.array([1.0, 0.05, 0.0]) / math.hypot(1.0, 0.05)
+    d = float(orb.point(seg, tau) @ th)
+    hits = orb.intersections(th, d)
+    assert len(hits) == 1                           # the full circle's other crossing is at -84.3 deg
+    assert crofton.M_point(orb, seg, tau, th) == 1.0
+    # with the normal turned so both crossings lie on the half circle, they share the weight
+    th2 = np.array([0.6, 0.8, 0.0])
+    hits2 = orb.intersections(th2, float(orb.point(seg, tau) @ th2))
+    assert len(hits2) == 2
+    assert abs(sum(crofton.M_point(orb, s_, t_, th2) for s_, t_ in hits2) - 1.0) < 1e-12
+    # the vectorised closed form agrees with the per-bin search on this orbit
+    g = small_grid(n_theta=12)
+    bins = [(k, m) for k in range(0, 12, 3) for m in range(0, g.n_s, 4)]
+    for v in (3, 32, 60):
+        Mc = crofton.M_view_closed_form(views, g, v)
+        Mg = crofton.M_view(views, g, v, bins=bins)
+        np.testing.assert_allclose([Mc[k, m] for k, m in bins], Mg, rtol=1e-10, atol=1e-12)
+
+
 def test_crofton_intersection_count_matches_brute_force_polyline():
     views = synth.circle_line_orbit(36, 11, 750.0, 1200.0, 200.0)
     orb = crofton.Orbit(views)
