@@ -111,12 +111,14 @@ class Orbit:
             ac = math.acos(max(-1.0, min(1.0, d / rho)))
             cand = [base + ac, base - ac] if ac > 0 else [base]
             if s["kind"] == "circle":
-                taus = [float(np.mod(c - s["lam0"], 2 * math.pi) + s["lam0"]) for c in cand]
                 if s["closed"]:
-                    return taus
-                # an open circle only holds the parameters its views cover
-                hi = self.tau_of_view(seg, s["count"] - 1)
-                return [min(t, hi) for t in taus if t <= hi + 1e-12]
+                    return [float(np.mod(c - s["lam0"], 2 * math.pi) + s["lam0"]) for c in cand]
+                # an open circle only holds the parameters its views cover; the
+                # window starts 1e-12 below the first view's parameter, so that a
+                # crossing at the first source point survives rounding (as on arcs)
+                lo, hi = self.tau_of_view(seg, 0), self.tau_of_view(seg, s["count"] - 1)
+                taus = [float(np.mod(c - lo + 1e-12, 2 * math.pi) + lo - 1e-12) for c in cand]
+                return [min(max(t, lo), hi) for t in taus if t <= hi + 1e-12]
             lo, hi = self.tau_of_view(seg, 0), self.tau_of_view(seg, s["count"] - 1)
             out = []
             for c in cand:
@@ -238,9 +240,9 @@ def M_view_closed_form(views, grid, v):
                     ok = hit & ((sign > 0) | (ac > 0))
                     if not sd["closed"]:
                         lo, hi = orbit.tau_of_view(seg, 0), orbit.tau_of_view(seg, sd["count"] - 1)
-                        tau = np.mod(tau - lo, 2 * math.pi) + lo
+                        tau = np.mod(tau - lo + 1e-12, 2 * math.pi) + lo - 1e-12
                         ok = ok & (tau <= hi + 1e-12)
-                        tau = np.minimum(tau, hi)
+                        tau = np.clip(tau, lo, hi)
                 else:
                     tau = np.mod(tau + math.pi, 2 * math.pi) - math.pi
                     lo, hi = orbit.tau_of_view(seg, 0), orbit.tau_of_view(seg, sd["count"] - 1)

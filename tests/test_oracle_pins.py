@@ -290,13 +290,31 @@ def test_crofton_open_circle_counts_only_covered_parameters():
     hits2 = orb.intersections(th2, float(orb.point(seg, tau) @ th2))
     assert len(hits2) == 2
     assert abs(sum(crofton.M_point(orb, s_, t_, th2) for s_, t_ in hits2) - 1.0) < 1e-12
-    # the vectorised closed form agrees with the per-bin search on this orbit
+    # every plane through the first or the last source point crosses the orbit
+    # there, and the weights of its crossings sum to 1
+    views = synth.circle_orbit(40, 750.0, 1200.0, start=0.3, span=math.pi)
+    orb = crofton.Orbit(views)
+    r = np.random.Generator(np.random.PCG64(9))
+    for v in (0, 39):
+        seg, tau = orb.locate(v)
+        for _ in range(200):
+            th = r.normal(size=3)
+            th /= np.linalg.norm(th)
+            hits = orb.intersections(th, float(orb.point(seg, tau) @ th))
+            assert any(abs(t_ - tau) < 1e-9 for _, t_ in hits)
+            assert abs(sum(crofton.M_point(orb, s_, t_, th) for s_, t_ in hits) - 1.0) < 1e-10
+    # the vectorised closed form agrees with the per-bin search on this orbit,
+    # wherever the filter uses the weight (on planes tangent to the orbit at every
+    # crossing eq. 9 is 0/0, the 1/n fallback depends on rounding, and c_geo = 0)
     g = small_grid(n_theta=12)
     bins = [(k, m) for k in range(0, 12, 3) for m in range(0, g.n_s, 4)]
-    for v in (3, 32, 60):
+    for v in (0, 3, 20, 39):
         Mc = crofton.M_view_closed_form(views, g, v)
         Mg = crofton.M_view(views, g, v, bins=bins)
-        np.testing.assert_allclose([Mc[k, m] for k, m in bins], Mg, rtol=1e-10, atol=1e-12)
+        cg = P.c_geo(g, views, v)
+        used = np.array([abs(cg[k, m]) > 1e-9 * np.abs(cg).max() for k, m in bins])
+        assert used.sum() >= 0.7 * len(bins)       # one angle row of the grid is tangent
+        np.testing.assert_allclose(np.array([Mc[k, m] for k, m in bins])[used], Mg[used], rtol=1e-10, atol=1e-12)
 
 
 def test_crofton_intersection_count_matches_brute_force_polyline():
