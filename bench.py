@@ -42,21 +42,27 @@ FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 9, "cone_bp": 
 # HBM bytes per call of a stage, from FETCH_SIZE and WRITE_SIZE counter runs of this
 # script (each scaled by what the counter reads for a 1 GiB copy; summaries in
 # profiles/c2_<dtype>_hbm_traffic.md).  A figure holds only for the kernel sources it
-# was measured on, identified by KERNEL_SOURCES_DIGEST; after any change to them the
-# roofline reports traffic as null until the counters are taken again.
+# was measured on, identified by the digest of the stage's kernel sources (the file
+# holding its kernels and launcher, and the shared internal header); after any change
+# to them the roofline reports traffic as null until the counters are taken again.
+STAGE_SOURCES = {
+    "weight_radon": ("radon2d.hip",), "detector_bp": ("radon2d.hip",), "detector_bp_adjoint": ("radon2d.hip",),
+    "filter": ("filter.hip",), "filter_adjoint": ("filter.hip",),
+    "cone_bp": ("cone.hip",), "cone_bp_adjoint": ("cone.hip",),
+}
 MEASURED_TRAFFIC = {
-    # (stage, storage dtype): (bytes per call, digest of the kernel sources)
-    ("cone_bp_adjoint", "f32"): (7_444_596_335 + 201_423_582,
-                                 "5561bfd8ab8fe9f5c258bd0dc5f8a03a79194c2840744979b966a5fa6e76feb8"),
+    # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
+    ("cone_bp_adjoint", "f32"): (7_443_487_697 + 201_424_414,
+                                 "a4cb10a2142e5ec9185597658402c8f4237b2fc230caf0abcaafe8c348f0707a"),
 }
 
 
-def kernel_sources_digest():
-    """sha256 over the names and bytes of every file in the package's csrc/."""
+def kernel_sources_digest(stage):
+    """sha256 over the names and bytes of the stage's kernel sources and dc_internal.h."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2410_14900_amd", "csrc", "*"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as fh:
+    for name in sorted(STAGE_SOURCES[stage] + ("dc_internal.h",)):
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2410_14900_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -272,6 +278,43 @@ def batched_c4(P, synth, args):
     }
 
 
+def crofton_baseline(P, plan, views, g, target):
+    """The analytic smooth Crofton weight of eq. 9 generated on the device for all
+    views (one timed call after a warm-up), and the reconstruction error it gives
+    without any learning, beside that of the constant weight 1/2."""
+    import torch
+    V, (K, S) = plan.n_views, plan.sino_shape
+    M = torch.empty((V, K, S), device="cuda")
+    segs, sid = views.meta["segments"], views.meta["sid"]
+    P.dc_crofton_weights(plan, segs, sid, M)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    P.dc_crofton_weights(plan, segs, sid, M)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    with torch.no_grad():
+        errs = {}
+        for name, W in (("crofton", M), ("half", torch.full_like(M, 0.5))):
+            f = P.reconstruct(plan, W, g=g, relu=True)
+            errs[name] = float((f - target).double().norm() / target.double().norm())
+            del f
+    return {"ms": round(ms, 2), "entries_per_s": V * K * S / (ms * 1e-3), "fine": 64,
+            "rel_error_untrained": round(errs["crofton"], 6), "rel_error_untrained_half": round(errs["half"], 6)}
+
+
+def crofton_oracle_rate(grid, views, n_bins=24):
+    """Entries per second of the oracle's eq. 9 (per-bin crossing search) on view 0."""
+    import numpy as np
+    from oracle import crofton
+    rng = np.random.Generator(np.random.PCG64(0))
+    bins = [(int(rng.integers(grid.n_theta)), int(rng.integers(grid.n_s))) for _ in range(n_bins)]
+    t0 = time.perf_counter()
+    crofton.M_view(views, grid, 0, bins=bins)
+    return n_bins / (time.perf_counter() - t0)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +391,9 @@ def main():
     log("f32 with the Gaussian weight layer: ms/step %.2f" % sm_ms, json.dumps(smoothing))
     del tr
     torch.cuda.empty_cache()
+    crof = crofton_baseline(P, plan, views, g, target)
+    log("Crofton weight (eq. 9) for all views:", json.dumps(crof))
+    torch.cuda.empty_cache()
     graph_ms = None
     if args.dtype != "f32":
         tr = Trainer(P, plan, g, target, torch.bfloat16)
@@ -362,7 +408,7 @@ def main():
     units, byts = r["work"][dom]
     t = r["kern"][dom] * 1e-3
     meas = MEASURED_TRAFFIC.get((dom, main_store))
-    traffic = meas[0] if meas and meas[1] == kernel_sources_digest() else None
+    traffic = meas[0] if meas and meas[1] == kernel_sources_digest(dom) else None
     if dom.startswith("filter"):
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(byts / t / 1e9, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -396,6 +442,7 @@ def main():
                        "kernels": b["per_kernel"], "speedup_vs_f32": round(r["ms"] / b["ms"], 3),
                        "rel_error": round(b["rel_error"], 6)}
     out["with_weight_smoothing"] = smoothing
+    out["crofton_weight"] = crof
     if graph_ms is not None:
         out["bf16_graph"] = {"value": nvox * V / (graph_ms * 1e-3), "ms_per_step": round(graph_ms, 3),
                              "speedup_vs_f32": round(r["ms"] / graph_ms, 3) if main_store == "f32" else None}
@@ -406,6 +453,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(grid, views, args.cpu_views)
+        out["crofton_weight"]["oracle_entries_per_s"] = round(crofton_oracle_rate(grid, views), 1)
     print(json.dumps(out), flush=True)
 
 

@@ -183,6 +183,48 @@ dc_status dc_smooth_weights_adjoint(dc_plan plan, const float* GMs, float* GM, d
  * own sample's volume); g float32 [V][nv][nu], views [v0, v0+nv) overwritten. */
 dc_status dc_project(dc_plan plan, const float* vol, float* g, int32_t v0, int32_t nv, hipStream_t stream);
 
+/* One analytic piece of a source orbit of radius sid around the origin, for the
+ * Crofton weight.  Views [start, start + count) of the plan sample it at
+ * parameters tau_k = p0 + k p1:
+ *   DC_SEG_CIRCLE   a = sid (cos tau, sin tau, 0)            p0 = lambda_0, p1 = dlambda
+ *   DC_SEG_ARC      a = sid (cos tau, 0, sin tau)            p0 = phi_0, p1 = dphi
+ *   DC_SEG_LINE     a = (sid, 0, tau)                        p0 = z_0, p1 = dz
+ *   DC_SEG_SINUSOID a = sid (cos phi cos tau, cos phi sin tau, sin phi),
+ *                   phi = phi_max cos(freq tau), tau over one turn   p0 = theta_0, p1 = dtheta
+ * closed = 1 for a curve that closes on itself (no end taper).  A sinusoid must
+ * be closed, and a closed circle or sinusoid must span one turn (count p1 = 2 pi). */
+typedef enum { DC_SEG_CIRCLE = 1, DC_SEG_ARC = 2, DC_SEG_LINE = 3, DC_SEG_SINUSOID = 4 } dc_seg_kind;
+typedef struct {
+  int32_t kind, start, count, closed;
+  double p0, p1, phi_max, freq;
+} dc_orbit_segment;
+
+/* The smooth Crofton redundancy weight of eq. 9 (Defrise & Clack's smooth
+ * replacement of 1/n, Sec. 2.4) on the plan's Radon grid:
+ *   M[v][k][m] = |a'(tau_v) . theta|^m_exp c(tau_v) / sum_alpha |a'(tau_alpha) . theta|^m_exp c(tau_alpha),
+ *   theta = (D n_mu_k + s_m l_z) / sqrt(s_m^2 + D^2),
+ * the sum running over every orbit parameter tau_alpha whose source point lies in
+ * the plane through a(tau_v) with normal theta.  a' is the tangent per view step
+ * (p1 a'(tau)); c = 1 on closed segments, and on open ones a raised-cosine ramp
+ * over the fraction `taper` of the parameter range at each end, floored at
+ * c_floor.  Where the sum is at most 1e-18 |a'(tau_v)|^m_exp (a plane tangent to
+ * the orbit wherever it meets it), M = 1 / max(1, number of crossings).
+ * Crossings are solved in closed form on circles, arcs and lines.  On a sinusoid
+ * the plane function is sampled at fine * count points tau_j = p0 + (j + 1/2) 2 pi / (fine count),
+ * every sign change (a zero sample counts on both sides, and the interval
+ * across the end of the turn) is refined by 80 bisection steps, and the
+ * crossing is the midpoint of the final interval.
+ * segs (host) partition the plan's views in order; one scan per plan
+ * (n_samples = 1, else DC_ENOTSUP); at most 16 segments; m_exp >= 1,
+ * 0 < taper <= 0.5, 0 < c_floor <= 1, fine >= 1 (DC_EINVAL otherwise).
+ * M float32 [V][n_theta][n_s], views [v0, v0+nv) overwritten.  work: device
+ * buffer of dc_crofton_workspace_bytes() bytes owned by the caller (the sampled
+ * sinusoid points). */
+size_t dc_crofton_workspace_bytes(const dc_orbit_segment* segs, int32_t n_segs, int32_t fine);
+dc_status dc_crofton_weights(dc_plan plan, const dc_orbit_segment* segs, int32_t n_segs, double sid, int32_t m_exp,
+                             double taper, double c_floor, int32_t fine, float* M, int32_t v0, int32_t nv,
+                             void* work, size_t work_bytes, hipStream_t stream);
+
 /* The structural term of the training loss (eq. 13), read as the standard 3D SSIM:
  * Gaussian window of standard deviation 1.5 and 11 taps per axis, C1 = (0.01 L)^2,
  * C2 = (0.03 L)^2 with L = data_range, mean over the positions where the whole

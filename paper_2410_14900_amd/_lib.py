@@ -34,6 +34,14 @@ class DcView(ctypes.Structure):
                 ("ey", c_double * 3), ("tangent", c_double * 3)]
 
 
+class DcOrbitSegment(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("start", c_int32), ("count", c_int32), ("closed", c_int32),
+                ("p0", c_double), ("p1", c_double), ("phi_max", c_double), ("freq", c_double)]
+
+
+DC_SEG_CIRCLE, DC_SEG_ARC, DC_SEG_LINE, DC_SEG_SINUSOID = 1, 2, 3, 4
+
+
 class DcError(RuntimeError):
     def __init__(self, status, where, msg):
         self.status = status
@@ -63,6 +71,9 @@ SIGNATURES = {
     "dc_smooth_weights": (_i, [_p, _vp, _vp, c_double, _i, _i, _i, _vp]),
     "dc_smooth_weights_adjoint": (_i, [_p, _vp, _vp, c_double, _i, _i, _i, _vp]),
     "dc_project": (_i, [_p, _vp, _vp, _i, _i, _vp]),
+    "dc_crofton_workspace_bytes": (c_size_t, [POINTER(DcOrbitSegment), _i, _i]),
+    "dc_crofton_weights": (_i, [_p, POINTER(DcOrbitSegment), _i, c_double, _i, c_double, c_double, _i, _vp, _i, _i,
+                                _vp, c_size_t, _vp]),
     "dc_ssim_workspace_bytes": (c_size_t, [_i, _i, _i]),
     "dc_ssim": (_i, [_vp, _vp, _i, _i, _i, c_float, _vp, _vp, _vp, c_size_t, _vp]),
 }

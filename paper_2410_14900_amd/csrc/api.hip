@@ -567,6 +567,60 @@ dc_status dc_project(dc_plan plan, const float* vol, float* g, int32_t v0, int32
   return launched(launch_project(p, vol, g, v0, nv, stream), "dc_project");
 }
 
+static dc_status check_segments(const dc_orbit_segment* segs, int32_t n_segs, int32_t fine, int n_views) {
+  if (!segs) return fail(DC_EINVAL, "segs is NULL");
+  if (n_segs < 1 || n_segs > crofton_max_segments())
+    return fail(DC_EINVAL, "between 1 and " + std::to_string(crofton_max_segments()) + " orbit segments");
+  if (fine < 1) return fail(DC_EINVAL, "fine must be at least 1");
+  long long next = 0, samples = 0;
+  for (int i = 0; i < n_segs; ++i) {
+    const dc_orbit_segment& s = segs[i];
+    const std::string id = "segment " + std::to_string(i) + ": ";
+    if (s.kind < DC_SEG_CIRCLE || s.kind > DC_SEG_SINUSOID) return fail(DC_EINVAL, id + "unknown kind");
+    if (s.start != next || s.count < 1) return fail(DC_EINVAL, id + "segments must cover the views in order");
+    next += s.count;
+    if (!std::isfinite(s.p0) || !std::isfinite(s.p1) || s.p1 == 0.0) return fail(DC_EINVAL, id + "bad parameters");
+    if (s.closed != 0 && s.closed != 1) return fail(DC_EINVAL, id + "closed must be 0 or 1");
+    if ((s.kind == DC_SEG_ARC || s.kind == DC_SEG_LINE) && s.closed) return fail(DC_EINVAL, id + "arcs and lines are open");
+    if (s.kind == DC_SEG_SINUSOID && !s.closed) return fail(DC_EINVAL, id + "a sinusoid must be closed");
+    if (!s.closed && s.count < 2) return fail(DC_EINVAL, id + "an open segment needs two views");
+    if (s.closed && std::fabs(s.count * s.p1 - 2.0 * M_PI) > 1e-9)
+      return fail(DC_EINVAL, id + "a closed segment must span one turn (count * p1 = 2 pi)");
+    if (s.kind == DC_SEG_SINUSOID) {
+      if (!std::isfinite(s.phi_max) || !std::isfinite(s.freq)) return fail(DC_EINVAL, id + "bad sinusoid");
+      samples += (long long)fine * s.count;
+    }
+  }
+  if (next != n_views) return fail(DC_EINVAL, "segments must cover all views of the plan");
+  if (samples > (1ll << 24)) return fail(DC_ENOTSUP, "more than 2^24 sinusoid samples");
+  return DC_OK;
+}
+
+size_t dc_crofton_workspace_bytes(const dc_orbit_segment* segs, int32_t n_segs, int32_t fine) {
+  if (!segs || n_segs < 1 || n_segs > crofton_max_segments() || fine < 1) return 0;
+  return crofton_workspace_bytes(segs, n_segs, fine);
+}
+
+dc_status dc_crofton_weights(dc_plan plan, const dc_orbit_segment* segs, int32_t n_segs, double sid, int32_t m_exp,
+                             double taper, double c_floor, int32_t fine, float* M, int32_t v0, int32_t nv,
+                             void* work, size_t work_bytes, hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  if (p.n_samples != 1) return fail(DC_ENOTSUP, "the Crofton weight needs a plan of one scan");
+  DC_TRY(check_segments(segs, n_segs, fine, p.n_views));
+  if (!(sid > 0.0) || !std::isfinite(sid)) return fail(DC_EINVAL, "sid must be positive");
+  if (m_exp < 1 || m_exp > 16) return fail(DC_EINVAL, "m_exp must be in [1, 16]");
+  if (!(taper > 0.0 && taper <= 0.5)) return fail(DC_EINVAL, "taper must be in (0, 0.5]");
+  if (!(c_floor > 0.0 && c_floor <= 1.0)) return fail(DC_EINVAL, "c_floor must be in (0, 1]");
+  DC_TRY(check_ptr(M, "M"));
+  DC_TRY(check_ptr(work, "work"));
+  if (work_bytes < crofton_workspace_bytes(segs, n_segs, fine))
+    return fail(DC_ESHAPE, "workspace smaller than dc_crofton_workspace_bytes()");
+  if (nv == 0) return DC_OK;
+  return launched(launch_crofton(p, segs, n_segs, sid, m_exp, taper, c_floor, fine, M, v0, nv, work, stream),
+                  "dc_crofton_weights");
+}
+
 size_t dc_ssim_workspace_bytes(int32_t nz, int32_t ny, int32_t nx) {
   if (nz < 11 || ny < 11 || nx < 11) return 0;
   return ssim_workspace_bytes(nz, ny, nx);

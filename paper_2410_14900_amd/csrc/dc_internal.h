@@ -112,6 +112,13 @@ hipError_t launch_smooth(const Plan& p, const float* in, float* out, double sigm
 // Siddon cone-beam projector (project.hip)
 hipError_t launch_project(const Plan& p, const float* vol, float* g, int v0, int nv, hipStream_t s);
 
+// smooth Crofton weight of eq. 9 (crofton.hip); segments already validated
+int crofton_max_segments();
+size_t crofton_workspace_bytes(const dc_orbit_segment* segs, int n_segs, int fine);
+hipError_t launch_crofton(const Plan& p, const dc_orbit_segment* segs, int n_segs, double sid, int m_exp,
+                          double taper, double c_floor, int fine, float* M, int v0, int nv, void* work,
+                          hipStream_t s);
+
 // 3D SSIM and its gradient (ssim.hip)
 size_t ssim_workspace_bytes(int nz, int ny, int nx);
 hipError_t launch_ssim(const float* x, const float* y, int nz, int ny, int nx, float L, float* ssim, float* grad,

@@ -231,6 +231,40 @@ def dc_smooth_weights_adjoint(plan, GMs, GM, sigma=20.0, radius=60, v0=0, nv=Non
     return GM
 
 
+_SEG_KINDS = {"circle": _lib.DC_SEG_CIRCLE, "arc": _lib.DC_SEG_ARC, "line": _lib.DC_SEG_LINE,
+              "sinusoid": _lib.DC_SEG_SINUSOID}
+_SEG_PARAMS = {"circle": ("lam0", "dlam"), "arc": ("phi0", "dphi"), "line": ("z0", "dz"), "sinusoid": ("th0", "dth")}
+
+
+def make_segments(segments):
+    """ctypes array of dc_orbit_segment from analytic segment descriptions (dicts
+    with kind, start, count, closed and the kind's parameters, as synth's orbits
+    carry them in views.meta["segments"])."""
+    buf = (_lib.DcOrbitSegment * len(segments))()
+    for i, s in enumerate(segments):
+        if s["kind"] not in _SEG_KINDS:
+            raise ValueError("no analytic Crofton weight for orbit segments of kind %r" % s["kind"])
+        a, b = _SEG_PARAMS[s["kind"]]
+        buf[i] = _lib.DcOrbitSegment(_SEG_KINDS[s["kind"]], int(s["start"]), int(s["count"]), int(bool(s["closed"])),
+                                     float(s[a]), float(s[b]), float(s.get("phi_max", 0.0)), float(s.get("freq", 0.0)))
+    return buf
+
+
+def dc_crofton_weights(plan, segments, sid, M, m_exp=2, taper=0.05, c_floor=0.01, fine=64, v0=0, nv=None,
+                       stream=None):
+    """Smooth Crofton weight of eq. 9 into M [V][n_theta][n_s] for views [v0, v0+nv)."""
+    _need(M, "M", (plan.n_views,) + plan.sino_shape)
+    v0, nv = _range(plan, v0, nv)
+    segs = make_segments(segments)
+    L = _lib.lib()
+    nbytes = L.dc_crofton_workspace_bytes(segs, len(segs), int(fine))
+    work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=M.device)
+    check(L.dc_crofton_weights(plan.handle, segs, len(segs), float(sid), int(m_exp), float(taper), float(c_floor),
+                               int(fine), _ptr(M), v0, nv, _ptr(work), nbytes, _stream(stream)),
+          "dc_crofton_weights")
+    return M
+
+
 def dc_ssim(x, y, data_range, grad=False, stream=None):
     """Mean 3D SSIM of x against y (volumes [nz][ny][nx]) and, with grad=True, its
     gradient w.r.t. x.  Returns (ssim as a 1-element tensor, grad or None)."""

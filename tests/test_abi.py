@@ -85,3 +85,18 @@ def test_batched_plan_rejects_more_samples_than_the_backprojection_grid_holds(P)
     with pytest.raises(P.DcError, match="DC_ENOTSUP"):
         P.Plan(g, views, first_view=first)
 
+
+
+def test_crofton_workspace_size_is_host_only():
+    """The sample table holds 3 doubles per sinusoid sample (fine * count of them),
+    plus 256 bytes of alignment slack; closed-form segments need none."""
+    import synth
+    from paper_2410_14900_amd import _lib, ops
+    L = _lib.lib()
+    sv = synth.sinusoid_orbit(24, 750.0, 1200.0)
+    arr = ops.make_segments(sv.meta["segments"])
+    assert L.dc_crofton_workspace_bytes(arr, 1, 64) == 3 * 64 * 24 * 8 + 256
+    ca = synth.circle_arc_orbit(12, 36, 750.0, 1200.0, 30.0)
+    assert L.dc_crofton_workspace_bytes(ops.make_segments(ca.meta["segments"]), 2, 64) == 256
+    assert L.dc_crofton_workspace_bytes(arr, 0, 64) == 0
+    assert L.dc_crofton_workspace_bytes(arr, 1, 0) == 0
