@@ -225,6 +225,20 @@ dc_status dc_crofton_weights(dc_plan plan, const dc_orbit_segment* segs, int32_t
                              double taper, double c_floor, int32_t fine, float* M, int32_t v0, int32_t nv,
                              void* work, size_t work_bytes, hipStream_t stream);
 
+/* Poisson noise on projection data (the simulated data of Sec. 3.3): for each
+ * element q of the line integrals p, lambda = photons exp(-mu p[q]) expected
+ * photons, a count N ~ Poisson(lambda), and out[q] = -ln(max(N, 1) / photons) / mu.
+ * The random numbers are those of the counter-based generator Philox4x64-10
+ * (Salmon et al., SC 2011) keyed (seed, 0): element e = e0 + q draws the blocks of
+ * counter (e, j, 0, 0), j = 0, 1, ..., each 64-bit word x giving the uniform
+ * ((x >> 11) + 1/2) 2^-53.  N is drawn by inversion for lambda < 10 and by
+ * Hoermann's transformed rejection (PTRS, 1993) otherwise, every decision in
+ * float64; results depend only on (seed, e, p[q], photons, mu), not on the launch.
+ * p, out float32 [n] (out may alias p); counts (nullable) int64 [n] receives N.
+ * Needs 0 < photons <= 1e12 and mu > 0 (DC_EINVAL).  Not tied to a plan. */
+dc_status dc_poisson_noise(const float* p, float* out, int64_t* counts, size_t n, double photons, double mu,
+                           uint64_t seed, uint64_t e0, hipStream_t stream);
+
 /* The structural term of the training loss (eq. 13), read as the standard 3D SSIM:
  * Gaussian window of standard deviation 1.5 and 11 taps per axis, C1 = (0.01 L)^2,
  * C2 = (0.03 L)^2 with L = data_range, mean over the positions where the whole

@@ -20,7 +20,8 @@ The count is drawn
   - for lambda >= 10 by Hoermann's transformed rejection with squeeze (PTRS;
     W. Hoermann, "The transformed rejection method for generating Poisson random
     variables", Insurance: Mathematics and Economics 12, 1993), two uniforms per
-    trial, trials taking the uniforms of the blocks in order.
+    trial, trials taking the uniforms of the blocks in order; after 256 rejected
+    trials (never reached in practice) the count is lambda rounded to nearest even.
 Every decision is taken in float64.
 """
 from __future__ import annotations
@@ -33,6 +34,7 @@ MASK64 = (1 << 64) - 1
 PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
 PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
 SMALL_LAMBDA = 10.0
+MAX_TRIALS = 256     # rejection trials; acceptance exceeds 0.8 per trial, so never reached
 
 
 def philox4x64(ctr, key, rounds=10):
@@ -86,7 +88,7 @@ def poisson_ptrs(lam, stream):
     a = -0.059 + 0.02483 * b
     inv_alpha = 1.1239 + 1.1328 / (b - 3.4)
     v_r = 0.9277 - 3.6224 / (b - 2.0)
-    while True:
+    for _ in range(MAX_TRIALS):
         U = stream.next() - 0.5
         V = stream.next()
         us = 0.5 - abs(U)
@@ -97,6 +99,7 @@ def poisson_ptrs(lam, stream):
             continue
         if math.log(V) + math.log(inv_alpha) - math.log(a / (us * us) + b) <= -lam + k * loglam - math.lgamma(k + 1.0):
             return k
+    return round(lam)
 
 
 def poisson_count(lam, seed, e):

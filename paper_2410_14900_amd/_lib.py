@@ -8,7 +8,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
-from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_size_t, c_uint32, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdcfbp.so")
@@ -74,6 +74,7 @@ SIGNATURES = {
     "dc_crofton_workspace_bytes": (c_size_t, [POINTER(DcOrbitSegment), _i, _i]),
     "dc_crofton_weights": (_i, [_p, POINTER(DcOrbitSegment), _i, c_double, _i, c_double, c_double, _i, _vp, _i, _i,
                                 _vp, c_size_t, _vp]),
+    "dc_poisson_noise": (_i, [_vp, _vp, _vp, c_size_t, c_double, c_double, c_uint64, c_uint64, _vp]),
     "dc_ssim_workspace_bytes": (c_size_t, [_i, _i, _i]),
     "dc_ssim": (_i, [_vp, _vp, _i, _i, _i, c_float, _vp, _vp, _vp, c_size_t, _vp]),
 }

@@ -621,6 +621,19 @@ dc_status dc_crofton_weights(dc_plan plan, const dc_orbit_segment* segs, int32_t
                   "dc_crofton_weights");
 }
 
+dc_status dc_poisson_noise(const float* p, float* out, int64_t* counts, size_t n, double photons, double mu,
+                           uint64_t seed, uint64_t e0, hipStream_t stream) {
+  if (!(photons > 0.0 && photons <= 1e12)) return fail(DC_EINVAL, "photons must be in (0, 1e12]");
+  if (!(mu > 0.0) || !std::isfinite(mu)) return fail(DC_EINVAL, "mu must be positive");
+  DC_TRY(check_ptr(p, "p"));
+  DC_TRY(check_ptr(out, "out"));
+  DC_TRY(check_ptr(counts, "counts", true));
+  if (n == 0) return DC_OK;
+  return launched(launch_poisson_noise(p, out, reinterpret_cast<long long*>(counts), n, photons, mu, seed, e0,
+                                       stream),
+                  "dc_poisson_noise");
+}
+
 size_t dc_ssim_workspace_bytes(int32_t nz, int32_t ny, int32_t nx) {
   if (nz < 11 || ny < 11 || nx < 11) return 0;
   return ssim_workspace_bytes(nz, ny, nx);

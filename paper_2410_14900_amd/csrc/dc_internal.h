@@ -119,6 +119,10 @@ hipError_t launch_crofton(const Plan& p, const dc_orbit_segment* segs, int n_seg
                           double taper, double c_floor, int fine, float* M, int v0, int nv, void* work,
                           hipStream_t s);
 
+// Poisson noise with the Philox4x64-10 generator (noise.hip)
+hipError_t launch_poisson_noise(const float* p, float* out, long long* counts, size_t n, double photons, double mu,
+                                unsigned long long seed, unsigned long long e0, hipStream_t s);
+
 // 3D SSIM and its gradient (ssim.hip)
 size_t ssim_workspace_bytes(int nz, int ny, int nx);
 hipError_t launch_ssim(const float* x, const float* y, int nz, int ny, int nx, float L, float* ssim, float* grad,

@@ -265,6 +265,18 @@ def dc_crofton_weights(plan, segments, sid, M, m_exp=2, taper=0.05, c_floor=0.01
     return M
 
 
+def dc_poisson_noise(p, out, photons, mu, seed, counts=None, e0=0, stream=None):
+    """Poisson-noisy line integrals of p (any float32 shape, contiguous) into out
+    (may be p); counts (int64, same shape, optional) receives the photon counts."""
+    if not p.is_contiguous() or p.dtype != torch.float32 or out.shape != p.shape or out.dtype != torch.float32:
+        raise ValueError("p and out must be contiguous float32 arrays of one shape")
+    if counts is not None and (counts.shape != p.shape or counts.dtype != torch.int64 or not counts.is_contiguous()):
+        raise ValueError("counts must be a contiguous int64 array of p's shape")
+    check(_lib.lib().dc_poisson_noise(_ptr(p), _ptr(out), _ptr(counts), p.numel(), float(photons), float(mu),
+                                      int(seed) & (2**64 - 1), int(e0), _stream(stream)), "dc_poisson_noise")
+    return out
+
+
 def dc_ssim(x, y, data_range, grad=False, stream=None):
     """Mean 3D SSIM of x against y (volumes [nz][ny][nx]) and, with grad=True, its
     gradient w.r.t. x.  Returns (ssim as a 1-element tensor, grad or None)."""
