@@ -52,8 +52,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (7_443_487_697 + 201_424_414,
-                                 "a4cb10a2142e5ec9185597658402c8f4237b2fc230caf0abcaafe8c348f0707a"),
+    ("cone_bp_adjoint", "f32"): (7_711_944_140 + 201_425_919,
+                                 "28940517cc4aef24d1e1c15c3c79531f861fbf1129fd456f233c3c1b080f5a61"),
+    ("weight_radon", "f32"): (1_060_338_595 + 521_260_347,
+                              "6227ade6ded5248f0ecb8b74cc5ed9bcea1a5ceff3c315e353f1d71de92150fb"),
 }
 
 

@@ -333,7 +333,12 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
   return r;
 }
 
-template <typename Tout>
+static constexpr int kBufferWord3 = 0x00020000;   // raw buffer resource word 3 on this GPU family
+
+// CLAMP: the volume is so wide and shallow that the byte offset of a z-segment
+// running past its last slice could pass 2^32; indices are then clamped into
+// the volume (and their values dropped) instead of left to the buffer's range check.
+template <typename Tout, bool CLAMP>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
                                                  const double* __restrict__ proj, const float* __restrict__ rmax2,
                                                  int v0, int nv, int tiles_u, int n_tiles, int max_terms,
@@ -341,6 +346,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
                                                  const int* __restrict__ first, int s_lo, int s_hi, int ngroups) {
   __shared__ double sL[kFV][4][4], sNegInvA[kFV][4];
   __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
+  __shared__ unsigned char sLay[kFROWS];   // z-layer of each listed row (sRow holds its y)
   __shared__ int sScan[256];
   __shared__ int sCount, sNL;
   __shared__ unsigned char sLayerOn[kFMaxLayers];
@@ -368,6 +374,10 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   }
   if (nvw <= 0) return;
   Gf += (size_t)smp * g.nx * g.ny * g.nz;
+  // reads go through a buffer resource spanning this sample's volume: offsets past
+  // its end return 0 (the range check), so segments need no clamping
+  const __amdgpu_buffer_rsrc_t vol =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Gf, (short)0, g.nx * g.ny * g.nz * 4, kBufferWord3);
   const int ti = tile % tiles_u, tj = tile / tiles_u;
   const int i0 = ti * kFTI, i1 = min(g.nu, i0 + kFTI);
   const int j0 = tj * kFTJ, j1 = min(g.nv, j0 + kFTJ);
@@ -456,7 +466,8 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       }
       if (ulo <= uhi) {
         const int slot = atomicAdd(&sCount, 1);
-        sRow[slot] = zs * g.ny + iy;
+        sRow[slot] = iy;
+        sLay[slot] = (unsigned char)zs;
         sXlo[slot] = (int)ulo;
         sPre[slot] = (int)(uhi - ulo) + 1;   // length for now
       }
@@ -488,20 +499,27 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
         const int mid = (lo + hi + 1) >> 1;
         if (sPre[mid] <= q) lo = mid; else hi = mid - 1;
       }
-      const int r = sRow[lo];
+      const int iy = sRow[lo];
       const int ix = sXlo[lo] + (q - sPre[lo]);
-      const int zs = r / g.ny, iy = r - zs * g.ny;
+      const int zs = sLay[lo];
       const int iz0 = zs * kFZS;
-      const int nzv = min(kFZS, g.nz - iz0);
-      // Issue all of the segment's loads before using any of them (branch-free:
-      // indices past the volume are clamped into it and their values dropped),
-      // so their latencies overlap instead of serialising.
+      // Issue all of the segment's loads before using any of them, so their
+      // latencies overlap instead of serialising.
       const int off = iz0 * plane + iy * g.nx + ix;
       float gv[kFZS];
+      if (CLAMP) {
+        const int nzv = min(kFZS, g.nz - iz0);
 #pragma unroll
-      for (int z = 0; z < kFZS; ++z) gv[z] = Gf[off + min(z, nzv - 1) * plane];
+        for (int z = 0; z < kFZS; ++z) gv[z] = Gf[off + min(z, nzv - 1) * plane];
 #pragma unroll
-      for (int z = 0; z < kFZS; ++z) gv[z] = z < nzv ? gv[z] : 0.f;
+        for (int z = 0; z < kFZS; ++z) gv[z] = z < nzv ? gv[z] : 0.f;
+      } else {
+        // slices past the last one lie past the end of the volume and read 0
+        const unsigned base = 4u * (unsigned)off, step = 4u * (unsigned)plane;
+#pragma unroll
+        for (int z = 0; z < kFZS; ++z)
+          gv[z] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(vol, (int)(base + z * step), 0, 0));
+      }
       for (int w = 0; w < nvw; ++w) {
         const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
         const float Sw = pick(S, w);
@@ -615,8 +633,14 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
     const float* src = f_relu ? p.d_masked : Gf;
-    hipLaunchKernelGGL((k_cone_fp<T>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, nv,
-                       tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, s_lo, s_hi, ngroups);
+    // the largest byte offset a segment forms: (nz rounded up to a whole layer) x plane x 4
+    const double top = (double)((p.kg.nz + kFZS - 1) / kFZS * kFZS) * p.kg.nx * p.kg.ny * 4.0;
+    if (top < 4294967296.0)
+      hipLaunchKernelGGL((k_cone_fp<T, false>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
+                         nv, tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, s_lo, s_hi, ngroups);
+    else
+      hipLaunchKernelGGL((k_cone_fp<T, true>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
+                         nv, tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, s_lo, s_hi, ngroups);
     return hipGetLastError();
   });
 }

@@ -120,3 +120,28 @@ def test_smoothing_arguments_are_checked_on_the_host(P):
                                   (2.0, g.n_s, "DC_ESHAPE")]:
         with pytest.raises(P.DcError, match=status):
             P.dc_smooth_weights(plan, M, M, sigma, radius)
+
+
+def test_wide_shallow_volume_uses_the_clamped_gather(P):
+    """An 8200 x 8192 x 1 volume: a 16-slice segment's byte offsets would pass 2^32,
+    so the cone adjoint reads with clamped indices instead of the buffer range
+    check.  The slice sits 100 mm above the orbit plane, so rays cross it
+    obliquely and few voxel centres share a detector cell.  Checked by the
+    adjoint identity with the (oracle-tested) cone BP."""
+    g = synth.Grid(nu=704, nv=128, du=1.0, dv=4.0, n_theta=8, n_s=synth.radon_bins(704, 128), ds=1.0,
+                   nx=8200, ny=8192, nz=1, vx=0.05, vy=0.05, vz=0.5, oz=100.0)
+    assert 16 * g.nx * g.ny * 4 > 2 ** 32
+    views = synth.circle_orbit(3, 750.0, 1200.0)
+    print("\n[gpu limits] 8200 x 8192 x 1", flush=True)
+    plan = P.Plan(g, views)
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    x = torch.randn((len(views), g.nv, g.nu), device="cuda", generator=gen)
+    y = torch.randn((g.nz, g.ny, g.nx), device="cuda", generator=gen)
+    Ax = torch.empty_like(y)
+    Aty = torch.empty_like(x)
+    P.dc_cone_bp(plan, x, Ax)
+    P.dc_cone_bp_adjoint(plan, y, Aty)
+    lhs = float((Ax.double() * y.double()).sum())
+    rhs = float((x.double() * Aty.double()).sum())
+    assert abs(lhs - rhs) <= 1e-6 * float(Ax.double().norm() * y.double().norm())
+    assert float(Aty.abs().max()) > 0
