@@ -492,12 +492,23 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
     if (threadIdx.x == 255) sPre[cnt] = run;   // total (thread 255 holds the last entries)
     __syncthreads();
     const int total = sPre[cnt];
-    // 3. flattened items: (row, x) -> a 16-voxel z-segment, projected on every view
-    for (int q = threadIdx.x; q < total; q += blockDim.x) {
-      int lo = 0, hi = cnt - 1;
-      while (lo < hi) {                       // last row with sPre[row] <= q
-        const int mid = (lo + hi + 1) >> 1;
-        if (sPre[mid] <= q) lo = mid; else hi = mid - 1;
+    // 3. flattened items: (row, x) -> a 16-voxel z-segment, projected on every view.
+    // Each wave takes a contiguous quarter of the items, 64 consecutive ones per
+    // pass, so a lane's next item lies 64 further on: its row is found once by
+    // bisection and then advanced by a short forward scan (rows hold ~15-30 items).
+    const int per_wave = (total + 3) >> 2;
+    const int qa = (threadIdx.x >> 6) * per_wave, qb = min(total, qa + per_wave);
+    int lo = -1;
+    for (int q = qa + (threadIdx.x & 63); q < qb; q += 64) {
+      if (lo < 0) {
+        int l = 0, h = cnt - 1;
+        while (l < h) {                       // last row with sPre[row] <= q
+          const int mid = (l + h + 1) >> 1;
+          if (sPre[mid] <= q) l = mid; else h = mid - 1;
+        }
+        lo = l;
+      } else {
+        while (sPre[lo + 1] <= q) ++lo;       // sPre[cnt] = total ends the scan
       }
       const int iy = sRow[lo];
       const int ix = sXlo[lo] + (q - sPre[lo]);
