@@ -52,9 +52,9 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (7_711_944_140 + 201_425_919,
-                                 "28940517cc4aef24d1e1c15c3c79531f861fbf1129fd456f233c3c1b080f5a61"),
-    ("weight_radon", "f32"): (1_060_338_595 + 521_260_347,
+    ("cone_bp_adjoint", "f32"): (13_222_172_255 + 201_425_855,
+                                 "c589460bc4fe5266ba40f8b40f117942457eaf66766a1417c086e38f0b0e70b9"),
+    ("weight_radon", "f32"): (1_060_919_533 + 521_262_659,
                               "6227ade6ded5248f0ecb8b74cc5ed9bcea1a5ceff3c315e353f1d71de92150fb"),
 }
 

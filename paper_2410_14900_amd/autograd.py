@@ -73,3 +73,17 @@ def reconstruct(plan, M, g=None, R=None, mode="analytic", store_dtype=torch.floa
         raise ValueError("recompute_R needs g")
     return _DCFBP.apply(M, R, g, plan, mode, store_dtype, relu, recompute_R,
                         None if smooth is None else (float(smooth[0]), int(smooth[1])))
+
+
+class DCFBP:
+    """The DC-FBP layer with its settings fixed: ``DCFBP(plan, mode, dtype,
+    recompute_R).apply(g, M)`` is ``reconstruct(plan, M, g=g, ...)`` (f, with exact
+    gradients for M through the chain of transposes)."""
+
+    def __init__(self, plan, mode="analytic", dtype=torch.float32, recompute_R=False, relu=False, smooth=None):
+        self.plan, self.mode, self.dtype = plan, mode, dtype
+        self.recompute_R, self.relu, self.smooth = recompute_R, relu, smooth
+
+    def apply(self, g, M):
+        return reconstruct(self.plan, M, g=g, mode=self.mode, store_dtype=self.dtype, relu=self.relu,
+                           recompute_R=self.recompute_R, smooth=self.smooth)

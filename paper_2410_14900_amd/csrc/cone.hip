@@ -40,7 +40,9 @@ __device__ __forceinline__ ColumnMap column_map(const double* __restrict__ P, in
   const double nu = fma((double)ix, P[4], fma((double)iy, P[5], fma((double)iz0, P[6], P[7])));
   const double nv = fma((double)ix, P[8], fma((double)iy, P[9], fma((double)iz0, P[10], P[11])));
   ColumnMap c;
-  const float rden = 1.0f / (float)den;
+  // iu0, jv0 only anchor the float offsets below (formed exactly in float64), so
+  // any integer within a pixel of the projection serves: the hardware reciprocal does
+  const float rden = __builtin_amdgcn_rcpf((float)den);
   c.iu0 = (int)floorf((float)nu * rden);
   c.jv0 = (int)floorf((float)nv * rden);
   c.den = (float)den;

@@ -268,6 +268,11 @@ def test_gradient_wrt_M(P, case):
     Gf = O.reconstruct(gp.astype(np.float64), M.astype(np.float64), g, views) - target
     ref = O.grad_M(gp.astype(np.float64), M.astype(np.float64), Gf, g, views)
     assert rel(host(Mt.grad), ref) < TOL_GRAD
+    # the layer form gives the same bits
+    M2 = dev(M).requires_grad_(True)
+    f2 = P.DCFBP(plan).apply(dev(gp), M2)
+    (0.5 * ((f2 - dev(target)) ** 2).sum()).backward()
+    assert torch.equal(f2, f) and torch.equal(M2.grad, Mt.grad)
 
 
 def test_gradient_wrt_M_through_the_smoothing_layer(P, case):
