@@ -52,10 +52,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_222_172_255 + 201_425_855,
+    ("cone_bp_adjoint", "f32"): (13_267_272_352 + 201_426_255,
                                  "c589460bc4fe5266ba40f8b40f117942457eaf66766a1417c086e38f0b0e70b9"),
-    ("weight_radon", "f32"): (1_060_919_533 + 521_262_659,
-                              "6227ade6ded5248f0ecb8b74cc5ed9bcea1a5ceff3c315e353f1d71de92150fb"),
+    ("weight_radon", "f32"): (1_058_772_952 + 521_261_697,
+                              "c58c3e6486906fc1c79178cdbc436501162339d25a413a72296957a8e458b90e"),
 }
 
 
