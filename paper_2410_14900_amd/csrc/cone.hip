@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf
   if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
 }
 
-static constexpr int kFMaxLayers = 64;
+static constexpr int kFMaxLayers = (1024 + kFZS - 1) / kFZS;   // z-layers of the deepest volume (nz <= 1024)
 
 static constexpr int kFV = 1;   // consecutive views per workgroup
 
