@@ -37,6 +37,14 @@ FP32_PEAK_TFLOPS = 157.3
 # stages, voxel-view pairs for the cone stages, sinogram bins for the filter
 FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 9, "cone_bp": 23,
                   "cone_bp_adjoint": 23, "detector_bp_adjoint": 9, "filter_adjoint": 10}
+# LDS bytes per unit the algorithms move: one 8-byte integer atomic per pixel-angle
+# (splat), one 8-byte (c, s) read per pixel-angle (interp), four 4-byte taps per
+# voxel-view (cone BP), two 8-byte atomics per voxel-view (cone transpose), a row
+# staged once per bin (filters, written and read).  Against 128 B per clock per CU
+# (the CDNA3 LDS figure; no CDNA4 one is published), 78.6 TB/s over 256 CUs.
+LDS_BYTES_PER_UNIT = {"weight_radon": 8, "filter": 8, "detector_bp": 8, "cone_bp": 16,
+                      "cone_bp_adjoint": 16, "detector_bp_adjoint": 8, "filter_adjoint": 8}
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 
 
 # HBM bytes per call of a stage, from FETCH_SIZE and WRITE_SIZE counter runs of this
@@ -392,6 +400,8 @@ def main():
             t = kern[st] * 1e-3
             per_kernel[st] = {"ms": round(kern[st], 3), "GB/s": round(byts / t / 1e9, 1),
                               "TFLOP/s": round(units * FLOPS_PER_UNIT[st] / t / 1e12, 2),
+                              "lds_TB/s": round(units * LDS_BYTES_PER_UNIT[st] / t / 1e12, 2),
+                              "lds_frac": round(units * LDS_BYTES_PER_UNIT[st] / t / 1e12 / LDS_PEAK_TBS, 3),
                               "units_per_s": units / t}
         results[store] = dict(ms=ms, kern=kern, per_kernel=per_kernel, work=work, rel_error=tr.rel_error())
         del tr
@@ -432,7 +442,9 @@ def main():
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
                 "algorithmic_bytes": byts,
-                "hbm_GBps": round(byts / t / 1e9, 1), "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 5)}
+                "hbm_GBps": round(byts / t / 1e9, 1), "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 5),
+                "lds_TBps": round(units * LDS_BYTES_PER_UNIT[dom] / t / 1e12, 2),
+                "lds_frac": round(units * LDS_BYTES_PER_UNIT[dom] / t / 1e12 / LDS_PEAK_TBS, 3)}
     out = {
         "metric": METRIC,
         "value": nvox * V / (r["ms"] * 1e-3),
