@@ -60,9 +60,9 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_267_272_352 + 201_426_255,
-                                 "c589460bc4fe5266ba40f8b40f117942457eaf66766a1417c086e38f0b0e70b9"),
-    ("weight_radon", "f32"): (1_058_772_952 + 521_261_697,
+    ("cone_bp_adjoint", "f32"): (13_358_087_084 + 201_426_031,
+                                 "a4ecf468a581901aa54e5638292ca1e55186c56830f6e53f81004424203cd606"),
+    ("weight_radon", "f32"): (1_059_184_202 + 521_261_309,
                               "c58c3e6486906fc1c79178cdbc436501162339d25a413a72296957a8e458b90e"),
 }
 

@@ -216,9 +216,12 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
         const float r = __builtin_amdgcn_rcpf(den);
         const float u = fmaf((float)z, c.ldu, c.lu) * r;
         const float w = fmaf((float)z, c.ldv, c.lv) * r;
-        const float fu0 = floorf(u), fw0 = floorf(w);
-        const float fu = u - fu0, fw = w - fw0;
-        const int i = oi + (int)fu0, j = oj + (int)fw0;
+        // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer u may
+        // give the cell below with fu = 1: the same value, inside the box margin)
+        const float yu = (u - 0.5f) + kRoundMagic, yw = (w - 0.5f) + kRoundMagic;
+        const float fu = u - (yu - kRoundMagic), fw = w - (yw - kRoundMagic);
+        const int i = oi + (int)(__float_as_uint(yu) - kRoundMagicBits);
+        const int j = oj + (int)(__float_as_uint(yw) - kRoundMagicBits);
         const int q = j * cur.w + i;
         const float a00 = t[q], a01 = t[q + 1], a10 = t[q + cur.w], a11 = t[q + cur.w + 1];
         const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
@@ -544,8 +547,12 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           const float rr = __builtin_amdgcn_rcpf(den);
           const float u = fmaf((float)z, c.ldu, c.lu) * rr;
           const float wv = fmaf((float)z, c.ldv, c.lv) * rr;
-          const float fu0 = floorf(u), fw0 = floorf(wv);
-          const int li = c.iu0 + (int)fu0 - (i0 - 1), lj = c.jv0 + (int)fw0 - (j0 - 1);
+          // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer may give
+          // the cell below with fraction 1: the same taps, and range checks as usual)
+          const float yu = (u - 0.5f) + kRoundMagic, yw = (wv - 0.5f) + kRoundMagic;
+          const float fu0 = yu - kRoundMagic, fw0 = yw - kRoundMagic;
+          const int li = c.iu0 + (int)(__float_as_uint(yu) - kRoundMagicBits) - (i0 - 1);
+          const int lj = c.jv0 + (int)(__float_as_uint(yw) - kRoundMagicBits) - (j0 - 1);
           const float x = gv[z];
           if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
             const float fu = u - fu0, fv = wv - fw0;
