@@ -60,10 +60,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_358_087_084 + 201_426_031,
+    ("cone_bp_adjoint", "f32"): (13_406_222_554 + 201_428_063,
                                  "a4ecf468a581901aa54e5638292ca1e55186c56830f6e53f81004424203cd606"),
-    ("weight_radon", "f32"): (1_059_184_202 + 521_261_309,
-                              "c58c3e6486906fc1c79178cdbc436501162339d25a413a72296957a8e458b90e"),
+    ("weight_radon", "f32"): (1_059_978_835 + 521_261_359,
+                              "f720c1c3d35659a001338dab0ae2da83cb6a35148cad0d72f6551afec08c1e47"),
 }
 
 
