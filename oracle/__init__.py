@@ -16,6 +16,7 @@ Modules
   smooth    -- the Gaussian smoothing layer of the learned weight (Sec. 3.1) and its transpose
   ssim      -- the 3D structural similarity of eq. 13's loss and its gradient
   noise     -- Poisson noise on projections (Sec. 3.3) from the counter-based Philox4x64-10 generator
+  adam      -- the Adam / AdamW update of the learned weight (Sec. 3.1)
 
 Every function here is pinned by a test against something other than itself
 (closed forms, invariants, the FDK equivalence on a circle, exact ball
