@@ -60,10 +60,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_406_222_554 + 201_428_063,
-                                 "a4ecf468a581901aa54e5638292ca1e55186c56830f6e53f81004424203cd606"),
-    ("weight_radon", "f32"): (1_059_978_835 + 521_261_359,
-                              "f720c1c3d35659a001338dab0ae2da83cb6a35148cad0d72f6551afec08c1e47"),
+    ("cone_bp_adjoint", "f32"): (13_421_348_552 + 201_424_927,
+                                 "65689d978d3f474965cadcfb90aca2381c17e6b1e78f3891e718b6956eb4c954"),
+    ("weight_radon", "f32"): (1_072_609_186 + 521_261_367,
+                              "263dfb0d5c9a9be39bdea8c2dc2620d4bb1055dbbcd3c175e5e58b800099f3ba"),
 }
 
 
@@ -122,15 +122,12 @@ def cpu_baseline(grid, views, n_views=1):
 
 
 def adam_(M, G, m, v, t, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8):
-    """Adam update of M in place from gradient G, with the step count t kept on the
-    device, in elementwise torch ops only (so the update can sit in a captured graph)."""
-    import torch
+    """Adam update of M in place from gradient G: the step count t (a float32 device
+    scalar) is advanced, then the library's fused update runs (one pass over the
+    arrays; both can sit in a captured graph)."""
+    import paper_2410_14900_amd as P
     t.add_(1.0)
-    m.mul_(b1).add_(G, alpha=1.0 - b1)
-    v.mul_(b2).addcmul_(G, G, value=1.0 - b2)
-    bc1 = 1.0 - torch.pow(b1, t)
-    bc2 = 1.0 - torch.pow(b2, t)
-    M.addcdiv_(m / bc1, (v / bc2).sqrt_().add_(eps), value=-lr)
+    P.dc_adam_step(M, G, m, v, t, lr, (b1, b2), eps)
 
 
 class Trainer:

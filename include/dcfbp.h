@@ -239,6 +239,18 @@ dc_status dc_crofton_weights(dc_plan plan, const dc_orbit_segment* segs, int32_t
 dc_status dc_poisson_noise(const float* p, float* out, int64_t* counts, size_t n, double photons, double mu,
                            uint64_t seed, uint64_t e0, hipStream_t stream);
 
+/* One Adam step (AdamW when weight_decay > 0) of a float32 parameter array: the
+ * paper trains the weight M with AdamW (Sec. 3.1).  In one pass,
+ *   M <- M (1 - lr weight_decay);  m <- b1 m + (1 - b1) G;  v <- b2 v + (1 - b2) G^2;
+ *   M <- M - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * with t = *step, a float32 on the device (>= 1) that the caller advances before
+ * the call, so the update can be captured in a graph.  M, m, v [n] updated in
+ * place, G [n] read; all float32, 16-byte aligned.  The hyperparameters are float64: 1 - b and
+ * the bias corrections are formed in float64 before rounding.  Needs 0 <= b1, b2 < 1,
+ * eps > 0, finite lr and weight_decay >= 0 (DC_EINVAL).  Not tied to a plan. */
+dc_status dc_adam_step(float* M, const float* G, float* m, float* v, size_t n, const float* step, double lr,
+                       double b1, double b2, double eps, double weight_decay, hipStream_t stream);
+
 /* The structural term of the training loss (eq. 13), read as the standard 3D SSIM:
  * Gaussian window of standard deviation 1.5 and 11 taps per axis, C1 = (0.01 L)^2,
  * C2 = (0.03 L)^2 with L = data_range, mean over the positions where the whole

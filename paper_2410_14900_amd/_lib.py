@@ -75,6 +75,7 @@ SIGNATURES = {
     "dc_crofton_weights": (_i, [_p, POINTER(DcOrbitSegment), _i, c_double, _i, c_double, c_double, _i, _vp, _i, _i,
                                 _vp, c_size_t, _vp]),
     "dc_poisson_noise": (_i, [_vp, _vp, _vp, c_size_t, c_double, c_double, c_uint64, c_uint64, _vp]),
+    "dc_adam_step": (_i, [_vp, _vp, _vp, _vp, c_size_t, _vp, c_double, c_double, c_double, c_double, c_double, _vp]),
     "dc_ssim_workspace_bytes": (c_size_t, [_i, _i, _i]),
     "dc_ssim": (_i, [_vp, _vp, _i, _i, _i, c_float, _vp, _vp, _vp, c_size_t, _vp]),
 }

@@ -1,0 +1,62 @@
+// Adam / AdamW update of the learned weight (the paper trains M with AdamW,
+// Sec. 3.1) in one pass over the arrays:
+//   M <- M (1 - lr wd);  m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+//   M <- M - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+// Reads M, G, m, v and writes M, m, v once (28 bytes per weight), where the same
+// update as separate elementwise operations passes over the arrays about a dozen
+// times.  The step count t is read from device memory, so the update can be
+// captured in a graph while the caller advances t.  float4 accesses over the
+// 16-byte aligned arrays, a scalar loop for the tail.
+#include <cmath>
+
+#include "dc_internal.h"
+
+namespace dc {
+
+struct AdamCoef {
+  float b1, omb1, b2, omb2, eps, lr, decay;   // omb = 1 - b and decay = 1 - lr wd, formed in float64
+  double db1, db2;                            // for the bias corrections
+};
+
+__device__ __forceinline__ void adam_one(float& M, float g, float& m, float& v, const AdamCoef& c, float inv_bc1,
+                                         float inv_bc2) {
+  m = fmaf(c.b1, m, c.omb1 * g);
+  v = fmaf(c.b2, v, c.omb2 * (g * g));
+  M = M * c.decay - c.lr * (m * inv_bc1) / (sqrtf(v * inv_bc2) + c.eps);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ M, const float* __restrict__ G,
+                                              float* __restrict__ m, float* __restrict__ v, size_t n,
+                                              const float* __restrict__ step, AdamCoef c) {
+  const double t = *step;
+  // bias corrections in float64: 1 - b^t loses digits to cancellation for small t
+  const float inv_bc1 = (float)(1.0 / (1.0 - pow(c.db1, t))), inv_bc2 = (float)(1.0 / (1.0 - pow(c.db2, t)));
+  const size_t n4 = n / 4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n4; q += stride) {
+    float4 a = reinterpret_cast<float4*>(M)[q];
+    const float4 g = reinterpret_cast<const float4*>(G)[q];
+    float4 mm = reinterpret_cast<float4*>(m)[q];
+    float4 vv = reinterpret_cast<float4*>(v)[q];
+    adam_one(a.x, g.x, mm.x, vv.x, c, inv_bc1, inv_bc2);
+    adam_one(a.y, g.y, mm.y, vv.y, c, inv_bc1, inv_bc2);
+    adam_one(a.z, g.z, mm.z, vv.z, c, inv_bc1, inv_bc2);
+    adam_one(a.w, g.w, mm.w, vv.w, c, inv_bc1, inv_bc2);
+    reinterpret_cast<float4*>(M)[q] = a;
+    reinterpret_cast<float4*>(m)[q] = mm;
+    reinterpret_cast<float4*>(v)[q] = vv;
+  }
+  for (size_t q = 4 * n4 + blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += stride)
+    adam_one(M[q], G[q], m[q], v[q], c, inv_bc1, inv_bc2);
+}
+
+hipError_t launch_adam(float* M, const float* G, float* m, float* v, size_t n, const float* step, double lr,
+                       double b1, double b2, double eps, double wd, hipStream_t s) {
+  const AdamCoef c{(float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, (float)lr,
+                   (float)(1.0 - lr * wd), b1, b2};
+  const size_t blocks = std::min<size_t>(8192, (n / 4 + 255) / 256 + 1);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, M, G, m, v, n, step, c);
+  return hipGetLastError();
+}
+
+}  // namespace dc

@@ -634,6 +634,21 @@ dc_status dc_poisson_noise(const float* p, float* out, int64_t* counts, size_t n
                   "dc_poisson_noise");
 }
 
+dc_status dc_adam_step(float* M, const float* G, float* m, float* v, size_t n, const float* step, double lr,
+                       double b1, double b2, double eps, double weight_decay, hipStream_t stream) {
+  if (!(b1 >= 0.0 && b1 < 1.0 && b2 >= 0.0 && b2 < 1.0)) return fail(DC_EINVAL, "betas must lie in [0, 1)");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(DC_EINVAL, "eps must be positive");
+  if (!std::isfinite(lr)) return fail(DC_EINVAL, "lr must be finite");
+  if (!(weight_decay >= 0.0) || !std::isfinite(weight_decay)) return fail(DC_EINVAL, "weight_decay must be >= 0");
+  DC_TRY(check_ptr(M, "M"));
+  DC_TRY(check_ptr(G, "G"));
+  DC_TRY(check_ptr(m, "m"));
+  DC_TRY(check_ptr(v, "v"));
+  if (!step) return fail(DC_EINVAL, "null pointer: step");
+  if (n == 0) return DC_OK;
+  return launched(launch_adam(M, G, m, v, n, step, lr, b1, b2, eps, weight_decay, stream), "dc_adam_step");
+}
+
 size_t dc_ssim_workspace_bytes(int32_t nz, int32_t ny, int32_t nx) {
   if (nz < 11 || ny < 11 || nx < 11) return 0;
   return ssim_workspace_bytes(nz, ny, nx);

@@ -123,6 +123,10 @@ hipError_t launch_crofton(const Plan& p, const dc_orbit_segment* segs, int n_seg
 hipError_t launch_poisson_noise(const float* p, float* out, long long* counts, size_t n, double photons, double mu,
                                 unsigned long long seed, unsigned long long e0, hipStream_t s);
 
+// fused Adam / AdamW step (adam.hip)
+hipError_t launch_adam(float* M, const float* G, float* m, float* v, size_t n, const float* step, double lr,
+                       double b1, double b2, double eps, double wd, hipStream_t s);
+
 // 3D SSIM and its gradient (ssim.hip)
 size_t ssim_workspace_bytes(int nz, int ny, int nx);
 hipError_t launch_ssim(const float* x, const float* y, int nz, int ny, int nx, float L, float* ssim, float* grad,

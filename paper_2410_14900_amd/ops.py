@@ -277,6 +277,20 @@ def dc_poisson_noise(p, out, photons, mu, seed, counts=None, e0=0, stream=None):
     return out
 
 
+def dc_adam_step(M, G, m, v, step, lr, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0, stream=None):
+    """One fused Adam (AdamW if weight_decay > 0) step of M in place; m, v are the
+    moment arrays and step a one-element float32 device tensor holding t >= 1."""
+    for name, t in (("M", M), ("G", G), ("m", m), ("v", v)):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.shape != M.shape:
+            raise ValueError("%s must be a contiguous float32 array of M's shape" % name)
+    if step.dtype != torch.float32 or step.numel() != 1:
+        raise ValueError("step must be a one-element float32 tensor")
+    check(_lib.lib().dc_adam_step(_ptr(M), _ptr(G), _ptr(m), _ptr(v), M.numel(), _ptr(step), float(lr),
+                                  float(betas[0]), float(betas[1]), float(eps), float(weight_decay), _stream(stream)),
+          "dc_adam_step")
+    return M
+
+
 def dc_ssim(x, y, data_range, grad=False, stream=None):
     """Mean 3D SSIM of x against y (volumes [nz][ny][nx]) and, with grad=True, its
     gradient w.r.t. x.  Returns (ssim as a 1-element tensor, grad or None)."""
