@@ -6,9 +6,9 @@
     M init U[-1, 0] (RAW mode: W is the whole redundancy weight of eq. 10),
     AdamW with a one-cycle learning rate between 0.1 and 1.
 
-Every step of the reconstruction, its transpose, the smoothing layer and the
-SSIM term runs in the HIP library; this module only wires them to torch's
-autograd and optimiser.
+Every step of the reconstruction, its transpose, the smoothing layer, the SSIM
+term and the AdamW update runs in the HIP library; this module only wires them
+to torch's autograd and learning-rate schedule.
 """
 from __future__ import annotations
 
@@ -31,6 +31,32 @@ class _SSIM(torch.autograd.Function):
     def backward(ctx, go):
         (g,) = ctx.saved_tensors
         return -go * g, None, None
+
+
+class FusedAdamW(torch.optim.Optimizer):
+    """AdamW whose update is the library's fused one-pass step (``dc_adam_step``);
+    the step count is kept on the device.  Parameter groups carry ``lr`` and
+    ``betas`` like torch's optimisers, so learning-rate (and momentum) schedules
+    apply unchanged.  Parameters must be contiguous float32 device tensors."""
+
+    def __init__(self, params, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0):
+        super().__init__(params, dict(lr=lr, betas=betas, eps=eps, weight_decay=weight_decay))
+
+    @torch.no_grad()
+    def step(self, closure=None):
+        loss = closure() if closure is not None else None
+        for group in self.param_groups:
+            for p in group["params"]:
+                if p.grad is None:
+                    continue
+                st = self.state[p]
+                if not st:
+                    st["m"], st["v"] = torch.zeros_like(p), torch.zeros_like(p)
+                    st["step"] = torch.zeros(1, device=p.device)
+                st["step"].add_(1.0)
+                ops.dc_adam_step(p, p.grad.contiguous(), st["m"], st["v"], st["step"], group["lr"],
+                                 group["betas"], group["eps"], group["weight_decay"])
+        return loss
 
 
 def ssim_loss(x, y, data_range=1.0):
@@ -57,7 +83,7 @@ def train_weights(plan, g, ref, steps, gamma=0.5, smooth=(20.0, 60), lr=(0.1, 1.
         M0 = -torch.rand((V,) + plan.sino_shape, device=g.device, generator=gen)   # U[-1, 0]
     M = M0.clone().requires_grad_(True)
     R = sinogram(plan, g)                     # depends on the data only
-    opt = torch.optim.AdamW([M], lr=lr[0], weight_decay=weight_decay)
+    opt = FusedAdamW([M], lr=lr[0], weight_decay=weight_decay)
     sched = torch.optim.lr_scheduler.OneCycleLR(opt, max_lr=lr[1], total_steps=max(2, steps),
                                                 div_factor=lr[1] / lr[0], final_div_factor=1.0)
     losses = []

@@ -87,3 +87,25 @@ def test_graph_replays_reproduce_eager_steps(P):
         torch.cuda.synchronize()
         assert torch.equal(M, eager[k]), k
         G.mul_(1.0)                             # eager work between replays
+
+
+def test_fused_optimizer_tracks_torch_adamw_under_one_cycle(P):
+    """train.FusedAdamW under the one-cycle schedule (which also cycles beta1)
+    against torch's AdamW with the same schedule, over ten steps."""
+    from paper_2410_14900_amd import train
+    gen = torch.Generator(device="cuda").manual_seed(8)
+    M0 = -torch.rand(100_003, device="cuda", generator=gen)
+    grads = [torch.randn(100_003, device="cuda", generator=gen) for _ in range(10)]
+    runs = []
+    for cls in (train.FusedAdamW, torch.optim.AdamW):
+        p = M0.clone().requires_grad_(True)
+        opt = cls([p], lr=0.1, weight_decay=0.01)
+        sched = torch.optim.lr_scheduler.OneCycleLR(opt, max_lr=1.0, total_steps=10, div_factor=10.0,
+                                                    final_div_factor=1.0)
+        for gr in grads:
+            p.grad = gr.clone()
+            opt.step()
+            sched.step()
+        runs.append(p.detach().clone())
+    err = float((runs[0] - runs[1]).abs().max() / runs[1].abs().max())
+    assert err < 1e-5, err
