@@ -272,6 +272,14 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
     }
     const int need = (int)std::ceil(worst / 256.0);
     p->bp_stage = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 0;
+    // den = U/D and num_u free of z on every view of a sample: a voxel column keeps
+    // one u and one weight per view, which the backprojection then forms once per
+    // column (decided per sample, so a batched plan computes what each scan's own
+    // plan does)
+    p->bp_zinv.assign(p->first.size() - 1, 1);
+    for (size_t smp = 0; smp + 1 < p->first.size(); ++smp)
+      for (int v = p->first[smp]; v < p->first[smp + 1]; ++v)
+        if (proj[12 * v + 2] != 0.0 || proj[12 * v + 6] != 0.0) p->bp_zinv[smp] = 0;
   }
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dst, bytes);

@@ -54,6 +54,47 @@ __device__ __forceinline__ ColumnMap column_map(const double* __restrict__ P, in
   return c;
 }
 
+// Column set-up when neither den nor num_u has a z-term (the detector's v axis
+// is parallel to z, as on circular orbits): the column keeps one u, so its tap
+// column i, the fraction fu and the weight (D/U)^2 hold for the whole segment,
+// and only v moves along z.
+struct ColumnMapZ {
+  float r2, fu;     // (D/U)^2 and the fraction of u in its cell
+  float w0m, dw;    // v - jv0 - 1/2 at the segment start and its z step
+  int i, jv0;       // detector column of the left taps, anchor row of v
+};
+
+__device__ __forceinline__ ColumnMapZ column_map_z(const double* __restrict__ P, int ix, int iy, int iz0) {
+  const double den = fma((double)ix, P[0], fma((double)iy, P[1], P[3]));
+  const double nu = fma((double)ix, P[4], fma((double)iy, P[5], P[7]));
+  const double nv = fma((double)ix, P[8], fma((double)iy, P[9], fma((double)iz0, P[10], P[11])));
+  const float rden = __builtin_amdgcn_rcpf((float)den);
+  const int iu0 = (int)floorf((float)nu * rden), jv0 = (int)floorf((float)nv * rden);
+  const float u = (float)fma(-(double)iu0, den, nu) * rden;
+  const float yu = (u - 0.5f) + kRoundMagic;
+  ColumnMapZ c;
+  c.fu = u - (yu - kRoundMagic);
+  c.i = iu0 + (int)(__float_as_uint(yu) - kRoundMagicBits);
+  c.jv0 = jv0;
+  c.r2 = rden * rden;
+  c.w0m = (float)fma(-(double)jv0, den, nv) * rden - 0.5f;
+  c.dw = (float)P[10] * rden;
+  return c;
+}
+
+static constexpr int kBufferWord3 = 0x00020000;   // raw buffer resource word 3 on this GPU family
+
+// raw buffer load of one storage element (offsets past the resource read 0)
+__device__ __forceinline__ void buffer_load_raw(__amdgpu_buffer_rsrc_t r, unsigned off, float& x) {
+  x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buffer_load_raw(__amdgpu_buffer_rsrc_t r, unsigned off, bf16_t& x) {
+  x.bits = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buffer_load_raw(__amdgpu_buffer_rsrc_t r, unsigned off, _Float16& x) {
+  x = __builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+}
+
 template <typename T>
 __device__ __forceinline__ float tap(const T* __restrict__ img, int i, int j, int nu, int nv) {
   return ((unsigned)i < (unsigned)nu && (unsigned)j < (unsigned)nv) ? to_f32(img[j * nu + i]) : 0.f;
@@ -100,8 +141,9 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
 }
 
 // STAGE = staged pixels per thread and view (the plan picks the smallest that
-// holds the largest footprint); STAGE == 0 selects direct global taps.
-template <typename T, int STAGE>
+// holds the largest footprint); STAGE == 0 selects direct global taps.  ZINV
+// (staged form only): no view's den or num_u depends on z.
+template <typename T, int STAGE, bool ZINV>
 __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
                                                  int nv, const int* __restrict__ first, int s_lo, int nzb) {
@@ -147,29 +189,32 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
     // raw storage values: converted to float32 only when written to LDS, so
     // no use of a load comes before the interpolation of the current view
     T stg[STAGE > 0 ? STAGE : 1];
-    // fetch view v's footprint into registers (zero outside the detector)
+    // fetch view v's footprint into registers (zero outside the detector and past
+    // the box).  The loads go through a resource spanning the view's image; a
+    // pixel off the detector takes an offset past its end, which reads 0, so no
+    // load sits behind a branch.
+    const unsigned img_bytes = (unsigned)(npix * sizeof(T));   // below 2^32: detectors are small
     auto load_stage = [&](int v, const Box& b) {
-      const T* img = gF + (size_t)v * npix;
-      const float invw = 1.0f / (float)b.w;
+      const __amdgpu_buffer_rsrc_t im =
+          __builtin_amdgcn_make_buffer_rsrc((void*)(gF + (size_t)v * npix), (short)0, (int)img_bytes, kBufferWord3);
+      // row = floor((e + 1/2) / w): the quotient lies at least 1/(2w) from an
+      // integer, while the hardware reciprocal's error stays below 1e-3/w for e < 4096
+      const float rw = __builtin_amdgcn_rcpf((float)b.w);
+      const int n = b.w * b.h;
 #pragma unroll
       for (int s = 0; s < STAGE; ++s) {
         const int e = tid + 256 * s;
-        T val{};
-        if (e < b.w * b.h) {
-          const int row = (int)(((float)e + 0.5f) * invw);
-          const int col = e - row * b.w;
-          const int ii = b.i_lo + col, jj = b.j_lo + row;
-          if ((unsigned)ii < (unsigned)g.nu && (unsigned)jj < (unsigned)g.nv) val = img[jj * g.nu + ii];
-        }
-        stg[s] = val;
+        const int row = (int)(((float)e + 0.5f) * rw);
+        const int ii = b.i_lo + (e - __mul24(row, b.w)), jj = b.j_lo + row;
+        const bool in = e < n && (unsigned)ii < (unsigned)g.nu && (unsigned)jj < (unsigned)g.nv;
+        buffer_load_raw(im, in ? (unsigned)(__mul24(jj, g.nu) + ii) * (unsigned)sizeof(T) : img_bytes, stg[s]);
       }
     };
-    auto store_stage = [&](int buf, const Box& b) {
+    // the whole slot is written (zeros past the box): nothing reads this buffer
+    // until the barrier that ends the current view
+    auto store_stage = [&](int buf) {
 #pragma unroll
-      for (int s = 0; s < STAGE; ++s) {
-        const int e = tid + 256 * s;
-        if (e < b.w * b.h) tile[buf][e] = to_f32(stg[s]);
-      }
+      for (int s = 0; s < STAGE; ++s) tile[buf][tid + 256 * s] = to_f32(stg[s]);
     };
     // Footprints are computed by one wave per view, two views ahead, and passed
     // on in a two-slot LDS ring: the box of view v sits in slot (v - v0) & 1 from
@@ -191,7 +236,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
       __syncthreads();
       cur = box_of(0);
       load_stage(v0, cur);
-      store_stage(0, cur);
+      store_stage(0);
     }
     __syncthreads();
     for (int v = v0; v < v0 + nv; ++v) {
@@ -203,34 +248,52 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
         load_stage(v + 1, nxt);
       }
       if (v + 2 < v0 + nv && wave == ((v - v0) & 3)) publish(v + 2, buf);
-      const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
       const float* t = tile[buf];
       // Tap indices need no clamping: every voxel of the block projects inside the
       // convex hull of its corners' projections, and the staged box extends that
       // hull by at least one pixel on each side (float rounding of the corners and
       // of the per-voxel walk is below 1e-4 pixel).
-      const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
+      if constexpr (ZINV) {
+        const ColumnMapZ c = column_map_z(proj + 12 * v, ix, iy, iz0);
+        const float* tc = t + (c.i - cur.i_lo);
+        // row index = bits(round(w - 1/2) + 1.5 * 2^23) - bias, in tile rows
+        const unsigned jbias = kRoundMagicBits - (unsigned)(c.jv0 - cur.j_lo);
 #pragma unroll
-      for (int z = 0; z < kZC; ++z) {
-        const float den = fmaf((float)z, c.dden, c.den);
-        const float r = __builtin_amdgcn_rcpf(den);
-        const float u = fmaf((float)z, c.ldu, c.lu) * r;
-        const float w = fmaf((float)z, c.ldv, c.lv) * r;
-        // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer u may
-        // give the cell below with fu = 1: the same value, inside the box margin)
-        const float yu = (u - 0.5f) + kRoundMagic, yw = (w - 0.5f) + kRoundMagic;
-        const float fu = u - (yu - kRoundMagic), fw = w - (yw - kRoundMagic);
-        const int i = oi + (int)(__float_as_uint(yu) - kRoundMagicBits);
-        const int j = oj + (int)(__float_as_uint(yw) - kRoundMagicBits);
-        const int q = j * cur.w + i;
-        const float a00 = t[q], a01 = t[q + 1], a10 = t[q + cur.w], a11 = t[q + cur.w + 1];
-        const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
-        acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
-        // keep the scheduler from hoisting every voxel's LDS reads at once
-        // (register pressure would cut occupancy to 2 waves per SIMD)
-        if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        for (int z = 0; z < kZC; ++z) {
+          const float wm = fmaf((float)z, c.dw, c.w0m);
+          const float yw = wm + kRoundMagic;
+          const float fw = (wm - (yw - kRoundMagic)) + 0.5f;
+          const float* r0 = tc + __umul24(__float_as_uint(yw) - jbias, (unsigned)cur.w);
+          const float a00 = r0[0], a01 = r0[1], a10 = r0[cur.w], a11 = r0[cur.w + 1];
+          const float top = fmaf(c.fu, a01 - a00, a00), bot = fmaf(c.fu, a11 - a10, a10);
+          acc[z] = fmaf(c.r2, fmaf(fw, bot - top, top), acc[z]);
+          if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
+        const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
+#pragma unroll
+        for (int z = 0; z < kZC; ++z) {
+          const float den = fmaf((float)z, c.dden, c.den);
+          const float r = __builtin_amdgcn_rcpf(den);
+          const float u = fmaf((float)z, c.ldu, c.lu) * r;
+          const float w = fmaf((float)z, c.ldv, c.lv) * r;
+          // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer u may
+          // give the cell below with fu = 1: the same value, inside the box margin)
+          const float yu = (u - 0.5f) + kRoundMagic, yw = (w - 0.5f) + kRoundMagic;
+          const float fu = u - (yu - kRoundMagic), fw = w - (yw - kRoundMagic);
+          const int i = oi + (int)(__float_as_uint(yu) - kRoundMagicBits);
+          const int j = oj + (int)(__float_as_uint(yw) - kRoundMagicBits);
+          const int q = __mul24(j, cur.w) + i;
+          const float a00 = t[q], a01 = t[q + 1], a10 = t[q + cur.w], a11 = t[q + cur.w + 1];
+          const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
+          acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
+          // keep the scheduler from hoisting every voxel's LDS reads at once
+          // (register pressure would cut occupancy to 2 waves per SIMD)
+          if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
       }
-      if (more) store_stage(buf ^ 1, nxt);
+      if (more) store_stage(buf ^ 1);
       __syncthreads();
       cur = nxt;
     }
@@ -338,7 +401,6 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
   return r;
 }
 
-static constexpr int kBufferWord3 = 0x00020000;   // raw buffer resource word 3 on this GPU family
 
 // CLAMP: the volume is so wide and shallow that the byte offset of a z-segment
 // running past its last slice could pass 2^32; indices are then clamped into
@@ -604,23 +666,49 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   }
 }
 
+static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0,
+                                     int nv, int s_lo, int s_hi, int nzb, bool zinv, hipStream_t s);
+
 hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0, int nv,
                           hipStream_t s) {
   int s_lo, s_hi;
   sample_span(p, v0, nv, &s_lo, &s_hi);
   const int nzb = (p.kg.nz + kZC - 1) / kZC;
+  // one launch per run of consecutive samples that take the same form
+  for (int a = s_lo; a <= s_hi;) {
+    int b = a;
+    while (b < s_hi && p.bp_zinv[b + 1] == p.bp_zinv[a]) ++b;
+    const hipError_t e = launch_cone_bp_run(p, gF, tF, f, acc, relu, v0, nv, a, b, nzb, p.bp_zinv[a] != 0, s);
+    if (e != hipSuccess) return e;
+    a = b + 1;
+  }
+  return hipSuccess;
+}
+
+static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0,
+                                     int nv, int s_lo, int s_hi, int nzb, bool zinv, hipStream_t s) {
   dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + kBY - 1) / kBY, nzb * (s_hi - s_lo + 1));
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
-#define DC_BP(ST)                                                                                          \
-  hipLaunchKernelGGL((k_cone_bp<T, ST>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, relu, \
-                     v0, nv, p.d_first, s_lo, nzb)
-    switch (p.bp_stage) {
-      case 4: DC_BP(4); break;
-      case 8: DC_BP(8); break;
-      case 12: DC_BP(12); break;
-      case 16: DC_BP(16); break;
-      default: DC_BP(0); break;
+#define DC_BP(ST, Z)                                                                                          \
+  hipLaunchKernelGGL((k_cone_bp<T, ST, Z>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, \
+                     relu, v0, nv, p.d_first, s_lo, nzb)
+    if (zinv) {
+      switch (p.bp_stage) {
+        case 4: DC_BP(4, true); break;
+        case 8: DC_BP(8, true); break;
+        case 12: DC_BP(12, true); break;
+        case 16: DC_BP(16, true); break;
+        default: DC_BP(0, false); break;
+      }
+    } else {
+      switch (p.bp_stage) {
+        case 4: DC_BP(4, false); break;
+        case 8: DC_BP(8, false); break;
+        case 12: DC_BP(12, false); break;
+        case 16: DC_BP(16, false); break;
+        default: DC_BP(0, false); break;
+      }
     }
 #undef DC_BP
     return hipGetLastError();

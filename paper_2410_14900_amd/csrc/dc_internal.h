@@ -74,6 +74,7 @@ struct Plan {
   // per-view arrays hold all samples' views, volumes one block per sample
   int n_samples = 1;
   std::vector<int> first;        // host copy, [n_samples + 1]
+  std::vector<char> bp_zinv;     // per sample: no view's den or num_u has a z-term (v axis along z)
   int* d_first = nullptr;        // [n_samples + 1]
   // plan-owned scratch: [0, V) per-view max |input| of the splat, [V, V + S) per-sample
   // max |Gf| of the cone adjoint (float bits, reduced with integer atomicMax).  Calls
