@@ -405,7 +405,10 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
 // CLAMP: the volume is so wide and shallow that the byte offset of a z-segment
 // running past its last slice could pass 2^32; indices are then clamped into
 // the volume (and their values dropped) instead of left to the buffer's range check.
-template <typename Tout, bool CLAMP>
+// ZINV: no view's den or num_u depends on z (as in the backprojection), so each
+// (segment, view) has one u, one tap column and one weight, and a segment whose
+// column misses the tile is skipped whole.
+template <typename Tout, bool CLAMP, bool ZINV>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
                                                  const double* __restrict__ proj, const float* __restrict__ rmax2,
                                                  int v0, int nv, int tiles_u, int n_tiles, int max_terms,
@@ -599,10 +602,38 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           gv[z] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(vol, (int)(base + z * step), 0, 0));
       }
       for (int w = 0; w < nvw; ++w) {
-        const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
         const float Sw = pick(S, w);
         unsigned long long* ab = sAB[w];
         unsigned long long* ce = sCE[w];
+        if constexpr (ZINV) {
+          const ColumnMapZ c = column_map_z(proj + 12 * (va + w), ix, iy, iz0);
+          const int li = c.i - (i0 - 1);
+          if ((unsigned)li > (unsigned)(i1 - i0)) continue;
+          const float K = c.r2 * Sw;   // (D/U)^2 S: every term stays below 2^21 (rmax2 carries a 1e-6 margin)
+          const unsigned jbias = kRoundMagicBits - (unsigned)(c.jv0 - (j0 - 1));
+#pragma unroll
+          for (int z = 0; z < kFZS; ++z) {
+            const float wm = fmaf((float)z, c.dw, c.w0m);
+            const float yw = wm + kRoundMagic;
+            const int lj = (int)(__float_as_uint(yw) - jbias);
+            const float x = gv[z];
+            if ((unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
+              const float fv = (wm - (yw - kRoundMagic)) + 0.5f;
+              const float gs = x * K;
+              const float gu = gs * c.fu;
+              const int qa = (int)(__float_as_uint(gs + kRoundMagic) - kRoundMagicBits);
+              const int qc = (int)(__float_as_uint(fmaf(gs, fv, kRoundMagic)) - kRoundMagicBits);
+              const unsigned hb =
+                  __float_as_uint(fmaf(gs, c.fu, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qa >> 31));
+              const unsigned he =
+                  __float_as_uint(fmaf(gu, fv, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qc >> 31));
+              atomicAdd(ab + lj * kFW + li, ((unsigned long long)hb << 32) | (unsigned)qa);
+              atomicAdd(ce + lj * kFW + li, ((unsigned long long)he << 32) | (unsigned)qc);
+            }
+          }
+          continue;
+        }
+        const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
 #pragma unroll
         for (int z = 0; z < kFZS; ++z) {
           const float den = fmaf((float)z, c.dden, c.den);
@@ -731,25 +762,37 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
   hipLaunchKernelGGL(k_vol_absmax, dim3(blocks, n_smp), dim3(256), 0, s, Gf + s_lo * n,
                      f_relu ? f_relu + s_lo * n : nullptr, n, gmax + s_lo, p.d_masked + s_lo * n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  int ngroups = 0;
-  for (int smp = s_lo; smp <= s_hi; ++smp) {
-    const int vb = std::max(v0, p.first[smp]), ve = std::min(v0 + nv, p.first[smp + 1]);
-    ngroups += (std::max(0, ve - vb) + kFV - 1) / kFV;
-  }
   const int n_tiles = tiles_u * tiles_v;
-  dim3 grid(8 * ((n_tiles + 7) / 8) * ngroups);
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
     const float* src = f_relu ? p.d_masked : Gf;
     // the largest byte offset a segment forms: (nz rounded up to a whole layer) x plane x 4
     const double top = (double)((p.kg.nz + kFZS - 1) / kFZS * kFZS) * p.kg.nx * p.kg.ny * 4.0;
-    if (top < 4294967296.0)
-      hipLaunchKernelGGL((k_cone_fp<T, false>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
-                         nv, tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, s_lo, s_hi, ngroups);
-    else
-      hipLaunchKernelGGL((k_cone_fp<T, true>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0,
-                         nv, tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, s_lo, s_hi, ngroups);
-    return hipGetLastError();
+    // one launch per run of consecutive samples that take the same form
+    for (int a = s_lo; a <= s_hi;) {
+      int b = a, ng = 0;
+      while (b < s_hi && p.bp_zinv[b + 1] == p.bp_zinv[a]) ++b;
+      for (int smp = a; smp <= b; ++smp) {
+        const int vb = std::max(v0, p.first[smp]), ve = std::min(v0 + nv, p.first[smp + 1]);
+        ng += (std::max(0, ve - vb) + kFV - 1) / kFV;
+      }
+      if (ng > 0) {
+        const dim3 grid(8 * ((n_tiles + 7) / 8) * ng);
+#define DC_FP(C, Z)                                                                                              \
+  hipLaunchKernelGGL((k_cone_fp<T, C, Z>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, nv, \
+                     tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, a, b, ng)
+        if (top < 4294967296.0) {
+          if (p.bp_zinv[a]) DC_FP(false, true); else DC_FP(false, false);
+        } else {
+          if (p.bp_zinv[a]) DC_FP(true, true); else DC_FP(true, false);
+        }
+#undef DC_FP
+        const hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess) return e2;
+      }
+      a = b + 1;
+    }
+    return hipSuccess;
   });
 }
 
