@@ -60,10 +60,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_421_348_552 + 201_424_927,
-                                 "65689d978d3f474965cadcfb90aca2381c17e6b1e78f3891e718b6956eb4c954"),
-    ("weight_radon", "f32"): (1_072_609_186 + 521_261_367,
-                              "263dfb0d5c9a9be39bdea8c2dc2620d4bb1055dbbcd3c175e5e58b800099f3ba"),
+    ("cone_bp_adjoint", "f32"): (13_279_291_768 + 201_424_047,
+                                 "314d26993f6388abeef6220ed79de9e72fb8c1f01c3a7fd913f44f3e5c308713"),
+    ("weight_radon", "f32"): (1_071_971_098 + 521_262_453,
+                              "b965a746162ef5a25f02755b383b0eb252e95e8717e408cf159c022cb439142e"),
 }
 
 
