@@ -45,6 +45,13 @@ FLOPS_PER_UNIT = {"weight_radon": 9, "filter": 10, "detector_bp": 9, "cone_bp": 
 LDS_BYTES_PER_UNIT = {"weight_radon": 8, "filter": 8, "detector_bp": 8, "cone_bp": 16,
                       "cone_bp_adjoint": 16, "detector_bp_adjoint": 8, "filter_adjoint": 8}
 LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+# The splats issue one 64-bit LDS integer atomic per pixel-angle.  Measured cost of
+# one wave-wide 64-bit atomic per CU on this GPU (a microbenchmark saturating the
+# LDS): 7.5 clocks when the 64 lanes hit consecutive words (the best layout),
+# 9.05 for the splat's pattern (lanes on pixel lines two apart), 12.9 when lane
+# pairs share a word.  The splats are reported against the best-layout figure.
+SPLAT_STAGES = ("weight_radon", "detector_bp_adjoint")
+LDS_ATOMIC_FLOOR_CLK = 7.5
 
 
 # HBM bytes per call of a stage, from FETCH_SIZE and WRITE_SIZE counter runs of this
@@ -75,6 +82,14 @@ def kernel_sources_digest(stage):
         with open(os.path.join(ROOT, "paper_2410_14900_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def atomic_clocks(units, t):
+    """Clocks per wave-wide 64-bit LDS atomic per CU for a splat of `units`
+    pixel-angles (one atomic each) taking t seconds, against the measured floor."""
+    clk = t * 256 * 2.4e9 / (units / 64.0)
+    return {"lds_atomic_clk": round(clk, 2), "lds_atomic_floor_clk": LDS_ATOMIC_FLOOR_CLK,
+            "lds_atomic_frac": round(LDS_ATOMIC_FLOOR_CLK / clk, 3)}
 
 
 def log(*a):
@@ -400,6 +415,8 @@ def main():
                               "lds_TB/s": round(units * LDS_BYTES_PER_UNIT[st] / t / 1e12, 2),
                               "lds_frac": round(units * LDS_BYTES_PER_UNIT[st] / t / 1e12 / LDS_PEAK_TBS, 3),
                               "units_per_s": units / t}
+            if st in SPLAT_STAGES:
+                per_kernel[st].update(atomic_clocks(units, t))
         results[store] = dict(ms=ms, kern=kern, per_kernel=per_kernel, work=work, rel_error=tr.rel_error())
         del tr
         torch.cuda.empty_cache()
@@ -442,6 +459,8 @@ def main():
                 "hbm_GBps": round(byts / t / 1e9, 1), "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 5),
                 "lds_TBps": round(units * LDS_BYTES_PER_UNIT[dom] / t / 1e12, 2),
                 "lds_frac": round(units * LDS_BYTES_PER_UNIT[dom] / t / 1e12 / LDS_PEAK_TBS, 3)}
+        if dom in SPLAT_STAGES:
+            roof.update(atomic_clocks(units, t))
     out = {
         "metric": METRIC,
         "value": nvox * V / (r["ms"] * 1e-3),
