@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
     // the box).  The loads go through a resource spanning the view's image; a
     // pixel off the detector takes an offset past its end, which reads 0, so no
     // load sits behind a branch.
-    const unsigned img_bytes = (unsigned)(npix * sizeof(T));   // below 2^32: detectors are small
+    const unsigned img_bytes = (unsigned)(npix * sizeof(T));   // < 2^31: the plan caps nu nv at 2^31 / 4
     auto load_stage = [&](int v, const Box& b) {
       const __amdgpu_buffer_rsrc_t im =
           __builtin_amdgcn_make_buffer_rsrc((void*)(gF + (size_t)v * npix), (short)0, (int)img_bytes, kBufferWord3);

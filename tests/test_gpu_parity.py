@@ -51,8 +51,24 @@ def ragged_case():
     return grid, views
 
 
+def rolled_circle_case():
+    """A circle whose detector is rolled 7 degrees about its normal: den has no
+    z-term but num_u does, so the cone stages must take their general form."""
+    grid = synth.Grid(nu=46, nv=38, du=1.2, dv=1.2, n_theta=44, n_s=synth.radon_bins(46, 38), ds=1.2,
+                      nx=28, ny=28, nz=26, vx=1.0, vy=1.0, vz=1.0)
+    v = synth.circle_orbit(10, 750.0, 1200.0)
+    c, s = math.cos(math.radians(7.0)), math.sin(math.radians(7.0))
+    ex, ey = c * v.ex + s * v.ey, -s * v.ex + c * v.ey
+    return grid, synth.Views(v.src, v.det_center, ex, ey, v.tangent, v.meta)
+
+
 CASES = {
     "ragged": ragged_case,
+    "rolled-circle": rolled_circle_case,
+    # circle plus a line along z: every view keeps the v axis along z (z-invariant cone forms)
+    "circle-line": lambda: (synth.Grid(nu=44, nv=40, du=1.2, dv=1.2, n_theta=40, n_s=synth.radon_bins(44, 40),
+                                       ds=1.2, nx=26, ny=26, nz=30, vx=1.0, vy=1.0, vz=1.0),
+                            synth.circle_line_orbit(8, 5, 750.0, 1200.0, 20.0)),
     "C1": lambda: synth.config_geometry("C1"),
     "arc": lambda: (synth.Grid(nu=48, nv=40, du=1.2, dv=1.2, n_theta=50, n_s=synth.radon_bins(48, 40), ds=1.2,
                                nx=30, ny=30, nz=30, vx=1.0, vy=1.0, vz=1.0),
