@@ -67,9 +67,9 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_279_291_768 + 201_424_047,
-                                 "314d26993f6388abeef6220ed79de9e72fb8c1f01c3a7fd913f44f3e5c308713"),
-    ("weight_radon", "f32"): (1_071_971_098 + 521_262_453,
+    ("cone_bp_adjoint", "f32"): (13_377_831_588 + 201_427_183,
+                                 "0edd22ccc4e79edfa0e0cda4a20c34f276f4d6f5b2c6be381718e448eb87e2be"),
+    ("weight_radon", "f32"): (1_073_042_814 + 521_259_629,
                               "b965a746162ef5a25f02755b383b0eb252e95e8717e408cf159c022cb439142e"),
 }
 
