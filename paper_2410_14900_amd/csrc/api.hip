@@ -193,7 +193,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
       frame[12 * v + 6 + c] = views[v].ex[c];
       frame[12 * v + 9 + c] = views[v].ey[c];
     }
-  std::vector<double> proj(12 * n);
+  std::vector<double> proj(12 * n), zrel(n);
   double max_cell_terms = 0.0;
   const double X0[3] = {-0.5 * (g->nx - 1) * g->vx + g->ox, -0.5 * (g->ny - 1) * g->vy + g->oy,
                         -0.5 * (g->nz - 1) * g->vz + g->oz};
@@ -232,6 +232,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
       umax = std::max(umax, den * D);
     }
     rmax2[v] = (float)((D / umin) * (D / umin) * (1.0 + 1e-6));
+    zrel[v] = std::fabs(P[2]) / (umin / D);   // largest relative change of den per voxel step in z
     max_cell_terms = std::max(max_cell_terms, cell_terms_bound(g, w, D, X0, umax));
     P[7] = dot3(rel0, w.ex) / g->du + 0.5 * (g->nu - 1) * dn0;
     P[11] = dot3(rel0, w.ey) / g->dv + 0.5 * (g->nv - 1) * dn0;
@@ -272,14 +273,22 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
     }
     const int need = (int)std::ceil(worst / 256.0);
     p->bp_stage = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 0;
-    // den = U/D and num_u free of z on every view of a sample: a voxel column keeps
-    // one u and one weight per view, which the backprojection then forms once per
-    // column (decided per sample, so a batched plan computes what each scan's own
-    // plan does)
-    p->bp_zinv.assign(p->first.size() - 1, 1);
-    for (size_t smp = 0; smp + 1 < p->first.size(); ++smp)
-      for (int v = p->first[smp]; v < p->first[smp + 1]; ++v)
-        if (proj[12 * v + 2] != 0.0 || proj[12 * v + 6] != 0.0) p->bp_zinv[smp] = 0;
+    // Form of the cone kernels, decided per sample (so a batched plan computes what
+    // each scan's own plan does).  den = U/D and num_u free of z on every view: a
+    // voxel column keeps one u and one weight per view, formed once per column.
+    // Otherwise, if den changes by at most 2.5e-4 of itself per voxel step, one
+    // Newton step from the previous voxel's reciprocal leaves a relative error of
+    // that change squared (< 6.3e-8, float rounding) and replaces the reciprocal.
+    p->cone_form.assign(p->first.size() - 1, kConeZinv);
+    for (size_t smp = 0; smp + 1 < p->first.size(); ++smp) {
+      bool zinv = true;
+      double worst = 0.0;
+      for (int v = p->first[smp]; v < p->first[smp + 1]; ++v) {
+        zinv = zinv && proj[12 * v + 2] == 0.0 && proj[12 * v + 6] == 0.0;
+        worst = std::max(worst, zrel[v]);
+      }
+      p->cone_form[smp] = zinv ? kConeZinv : worst <= 2.5e-4 ? kConeNewton : kConeGeneral;
+    }
   }
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dst, bytes);

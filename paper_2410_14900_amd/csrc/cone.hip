@@ -141,9 +141,9 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
 }
 
 // STAGE = staged pixels per thread and view (the plan picks the smallest that
-// holds the largest footprint); STAGE == 0 selects direct global taps.  ZINV
-// (staged form only): no view's den or num_u depends on z.
-template <typename T, int STAGE, bool ZINV>
+// holds the largest footprint); STAGE == 0 selects direct global taps.  FORM
+// (staged form only) is the plan's choice for the sample (ConeForm).
+template <typename T, int STAGE, int FORM>
 __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
                                                  int nv, const int* __restrict__ first, int s_lo, int nzb) {
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
       // convex hull of its corners' projections, and the staged box extends that
       // hull by at least one pixel on each side (float rounding of the corners and
       // of the per-voxel walk is below 1e-4 pixel).
-      if constexpr (ZINV) {
+      if constexpr (FORM == kConeZinv) {
         const ColumnMapZ c = column_map_z(proj + 12 * v, ix, iy, iz0);
         const float* tc = t + (c.i - cur.i_lo);
         // row index = bits(round(w - 1/2) + 1.5 * 2^23) - bias, in tile rows
@@ -272,10 +272,17 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
       } else {
         const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
         const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
+        // kConeNewton: 1/den by one Newton step from the previous voxel's reciprocal
+        // (den moves by at most 2.5e-4 of itself per voxel step, so the step's error,
+        // that change squared, is below float rounding): two FMAs instead of a
+        // quarter-rate reciprocal
+        float r = __builtin_amdgcn_rcpf(c.den);
 #pragma unroll
         for (int z = 0; z < kZC; ++z) {
-          const float den = fmaf((float)z, c.dden, c.den);
-          const float r = __builtin_amdgcn_rcpf(den);
+          if (z > 0) {
+            const float den = fmaf((float)z, c.dden, c.den);
+            r = FORM == kConeNewton ? fmaf(r, fmaf(-den, r, 1.0f), r) : __builtin_amdgcn_rcpf(den);
+          }
           const float u = fmaf((float)z, c.ldu, c.lu) * r;
           const float w = fmaf((float)z, c.ldv, c.lv) * r;
           // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer u may
@@ -405,10 +412,10 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
 // CLAMP: the volume is so wide and shallow that the byte offset of a z-segment
 // running past its last slice could pass 2^32; indices are then clamped into
 // the volume (and their values dropped) instead of left to the buffer's range check.
-// ZINV: no view's den or num_u depends on z (as in the backprojection), so each
-// (segment, view) has one u, one tap column and one weight, and a segment whose
-// column misses the tile is skipped whole.
-template <typename Tout, bool CLAMP, bool ZINV>
+// FORM (ConeForm) as in the backprojection; with kConeZinv each (segment, view)
+// has one u, one tap column and one weight, and a segment whose column misses
+// the tile is skipped whole.
+template <typename Tout, bool CLAMP, int FORM>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
                                                  const double* __restrict__ proj, const float* __restrict__ rmax2,
                                                  int v0, int nv, int tiles_u, int n_tiles, int max_terms,
@@ -605,7 +612,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
         const float Sw = pick(S, w);
         unsigned long long* ab = sAB[w];
         unsigned long long* ce = sCE[w];
-        if constexpr (ZINV) {
+        if constexpr (FORM == kConeZinv) {
           const ColumnMapZ c = column_map_z(proj + 12 * (va + w), ix, iy, iz0);
           const int li = c.i - (i0 - 1);
           if ((unsigned)li > (unsigned)(i1 - i0)) continue;
@@ -634,10 +641,13 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           continue;
         }
         const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
+        float rr = __builtin_amdgcn_rcpf(c.den);   // kConeNewton: Newton steps along z, as in the backprojection
 #pragma unroll
         for (int z = 0; z < kFZS; ++z) {
-          const float den = fmaf((float)z, c.dden, c.den);
-          const float rr = __builtin_amdgcn_rcpf(den);
+          if (z > 0) {
+            const float den = fmaf((float)z, c.dden, c.den);
+            rr = FORM == kConeNewton ? fmaf(rr, fmaf(-den, rr, 1.0f), rr) : __builtin_amdgcn_rcpf(den);
+          }
           const float u = fmaf((float)z, c.ldu, c.lu) * rr;
           const float wv = fmaf((float)z, c.ldv, c.lv) * rr;
           // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer may give
@@ -698,7 +708,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
 }
 
 static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0,
-                                     int nv, int s_lo, int s_hi, int nzb, bool zinv, hipStream_t s);
+                                     int nv, int s_lo, int s_hi, int nzb, int form, hipStream_t s);
 
 hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0, int nv,
                           hipStream_t s) {
@@ -708,8 +718,8 @@ hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, 
   // one launch per run of consecutive samples that take the same form
   for (int a = s_lo; a <= s_hi;) {
     int b = a;
-    while (b < s_hi && p.bp_zinv[b + 1] == p.bp_zinv[a]) ++b;
-    const hipError_t e = launch_cone_bp_run(p, gF, tF, f, acc, relu, v0, nv, a, b, nzb, p.bp_zinv[a] != 0, s);
+    while (b < s_hi && p.cone_form[b + 1] == p.cone_form[a]) ++b;
+    const hipError_t e = launch_cone_bp_run(p, gF, tF, f, acc, relu, v0, nv, a, b, nzb, p.cone_form[a], s);
     if (e != hipSuccess) return e;
     a = b + 1;
   }
@@ -717,30 +727,27 @@ hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, 
 }
 
 static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0,
-                                     int nv, int s_lo, int s_hi, int nzb, bool zinv, hipStream_t s) {
+                                     int nv, int s_lo, int s_hi, int nzb, int form, hipStream_t s) {
   dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + kBY - 1) / kBY, nzb * (s_hi - s_lo + 1));
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
 #define DC_BP(ST, Z)                                                                                          \
   hipLaunchKernelGGL((k_cone_bp<T, ST, Z>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, \
                      relu, v0, nv, p.d_first, s_lo, nzb)
-    if (zinv) {
-      switch (p.bp_stage) {
-        case 4: DC_BP(4, true); break;
-        case 8: DC_BP(8, true); break;
-        case 12: DC_BP(12, true); break;
-        case 16: DC_BP(16, true); break;
-        default: DC_BP(0, false); break;
-      }
-    } else {
-      switch (p.bp_stage) {
-        case 4: DC_BP(4, false); break;
-        case 8: DC_BP(8, false); break;
-        case 12: DC_BP(12, false); break;
-        case 16: DC_BP(16, false); break;
-        default: DC_BP(0, false); break;
-      }
+#define DC_BP_FORMS(ST)                                            \
+  switch (form) {                                                  \
+    case kConeZinv: DC_BP(ST, kConeZinv); break;                   \
+    case kConeNewton: DC_BP(ST, kConeNewton); break;               \
+    default: DC_BP(ST, kConeGeneral); break;                       \
+  }
+    switch (p.bp_stage) {
+      case 4: DC_BP_FORMS(4); break;
+      case 8: DC_BP_FORMS(8); break;
+      case 12: DC_BP_FORMS(12); break;
+      case 16: DC_BP_FORMS(16); break;
+      default: DC_BP(0, kConeGeneral); break;
     }
+#undef DC_BP_FORMS
 #undef DC_BP
     return hipGetLastError();
   });
@@ -771,7 +778,7 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
     // one launch per run of consecutive samples that take the same form
     for (int a = s_lo; a <= s_hi;) {
       int b = a, ng = 0;
-      while (b < s_hi && p.bp_zinv[b + 1] == p.bp_zinv[a]) ++b;
+      while (b < s_hi && p.cone_form[b + 1] == p.cone_form[a]) ++b;
       for (int smp = a; smp <= b; ++smp) {
         const int vb = std::max(v0, p.first[smp]), ve = std::min(v0 + nv, p.first[smp + 1]);
         ng += (std::max(0, ve - vb) + kFV - 1) / kFV;
@@ -781,10 +788,11 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
 #define DC_FP(C, Z)                                                                                              \
   hipLaunchKernelGGL((k_cone_fp<T, C, Z>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, nv, \
                      tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, a, b, ng)
-        if (top < 4294967296.0) {
-          if (p.bp_zinv[a]) DC_FP(false, true); else DC_FP(false, false);
-        } else {
-          if (p.bp_zinv[a]) DC_FP(true, true); else DC_FP(true, false);
+        const bool clamp = top >= 4294967296.0;
+        switch (p.cone_form[a]) {
+          case kConeZinv: if (clamp) DC_FP(true, kConeZinv); else DC_FP(false, kConeZinv); break;
+          case kConeNewton: if (clamp) DC_FP(true, kConeNewton); else DC_FP(false, kConeNewton); break;
+          default: if (clamp) DC_FP(true, kConeGeneral); else DC_FP(false, kConeGeneral); break;
         }
 #undef DC_FP
         const hipError_t e2 = hipGetLastError();

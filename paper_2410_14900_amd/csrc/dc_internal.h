@@ -48,6 +48,8 @@ struct KGrid {
 };
 
 // Plan: host copy of the geometry plus small device tables.
+enum ConeForm : char { kConeGeneral = 0, kConeNewton = 1, kConeZinv = 2 };
+
 struct Plan {
   int device = 0;
   dc_grid grid{};
@@ -74,7 +76,10 @@ struct Plan {
   // per-view arrays hold all samples' views, volumes one block per sample
   int n_samples = 1;
   std::vector<int> first;        // host copy, [n_samples + 1]
-  std::vector<char> bp_zinv;     // per sample: no view's den or num_u has a z-term (v axis along z)
+  // per sample, the form of the cone kernels: kConeGeneral, kConeNewton (den varies so
+  // slowly along z that a Newton step from the previous voxel gives 1/den) or kConeZinv
+  // (no view's den or num_u has a z-term: the detector's v axis stays along z)
+  std::vector<char> cone_form;
   int* d_first = nullptr;        // [n_samples + 1]
   // plan-owned scratch: [0, V) per-view max |input| of the splat, [V, V + S) per-sample
   // max |Gf| of the cone adjoint (float bits, reduced with integer atomicMax).  Calls
