@@ -67,10 +67,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_377_831_588 + 201_427_183,
-                                 "0edd22ccc4e79edfa0e0cda4a20c34f276f4d6f5b2c6be381718e448eb87e2be"),
-    ("weight_radon", "f32"): (1_073_042_814 + 521_259_629,
-                              "b965a746162ef5a25f02755b383b0eb252e95e8717e408cf159c022cb439142e"),
+    ("cone_bp_adjoint", "f32"): (13_657_093_779 + 201_422_463,
+                                 "451d9967401983c05defcd1ebdda81e8a4687a801e45bf6772dbdefcf92bd1f1"),
+    ("weight_radon", "f32"): (1_073_065_149 + 521_261_643,
+                              "2a75754a52dfd1914756097c5204291663a14a1f89068db2674609ca485e11c5"),
 }
 
 
