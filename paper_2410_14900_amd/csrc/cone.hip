@@ -624,7 +624,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
             const float yw = wm + kRoundMagic;
             const int lj = (int)(__float_as_uint(yw) - jbias);
             const float x = gv[z];
-            if ((unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
+            if (((unsigned)lj <= (unsigned)(j1 - j0)) & (x != 0.f)) {   // one branch, not two
               const float fv = (wm - (yw - kRoundMagic)) + 0.5f;
               const float gs = x * K;
               const float gu = gs * c.fu;
@@ -634,8 +634,9 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
                   __float_as_uint(fmaf(gs, c.fu, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qa >> 31));
               const unsigned he =
                   __float_as_uint(fmaf(gu, fv, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qc >> 31));
-              atomicAdd(ab + lj * kFW + li, ((unsigned long long)hb << 32) | (unsigned)qa);
-              atomicAdd(ce + lj * kFW + li, ((unsigned long long)he << 32) | (unsigned)qc);
+              const unsigned cell = __umul24((unsigned)lj, (unsigned)kFW) + li;   // lj < 2^24: 24-bit multiply
+              atomicAdd(ab + cell, ((unsigned long long)hb << 32) | (unsigned)qa);
+              atomicAdd(ce + cell, ((unsigned long long)he << 32) | (unsigned)qc);
             }
           }
           continue;
@@ -657,7 +658,8 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           const int li = c.iu0 + (int)(__float_as_uint(yu) - kRoundMagicBits) - (i0 - 1);
           const int lj = c.jv0 + (int)(__float_as_uint(yw) - kRoundMagicBits) - (j0 - 1);
           const float x = gv[z];
-          if ((unsigned)li <= (unsigned)(i1 - i0) && (unsigned)lj <= (unsigned)(j1 - j0) && x != 0.f) {
+          // bitwise rather than short-circuit: one branch per voxel
+          if (((unsigned)li <= (unsigned)(i1 - i0)) & ((unsigned)lj <= (unsigned)(j1 - j0)) & (x != 0.f)) {
             const float fu = u - fu0, fv = wv - fw0;
             const float gs = x * rr * rr * Sw;
             const float gu = gs * fu;
@@ -672,8 +674,9 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
             const unsigned he = __float_as_uint(fmaf(gu, fv, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qc >> 31));
             const unsigned long long w1 = ((unsigned long long)hb << 32) | (unsigned)qa;
             const unsigned long long w2 = ((unsigned long long)he << 32) | (unsigned)qc;
-            atomicAdd(ab + lj * kFW + li, w1);
-            atomicAdd(ce + lj * kFW + li, w2);
+            const unsigned cell = __umul24((unsigned)lj, (unsigned)kFW) + li;   // lj < 2^24: 24-bit multiply
+            atomicAdd(ab + cell, w1);
+            atomicAdd(ce + cell, w2);
           }
         }
       }
