@@ -67,9 +67,9 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_657_093_779 + 201_422_463,
-                                 "451d9967401983c05defcd1ebdda81e8a4687a801e45bf6772dbdefcf92bd1f1"),
-    ("weight_radon", "f32"): (1_073_065_149 + 521_261_643,
+    ("cone_bp_adjoint", "f32"): (14_001_825_319 + 201_422_079,
+                                 "ed05dd44992ac7f3e48dbf9e89c35fdee215777108dad7677f1d268b0afd4037"),
+    ("weight_radon", "f32"): (1_073_475_169 + 521_261_371,
                               "2a75754a52dfd1914756097c5204291663a14a1f89068db2674609ca485e11c5"),
 }
 
