@@ -109,7 +109,8 @@ dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_vi
  * Per-view arrays (g, R, M, H, gF and their gradients) hold all samples' views
  * back to back; volumes (f, Gf, f_relu) hold one [nz][ny][nx] block per sample,
  * in sample order, so every stage call serves all samples with one launch per
- * kernel.  A view range [v0, v0+nv) may span samples: dc_cone_bp writes the
+ * kernel (the cone stages: one per run of consecutive samples that take the same
+ * evaluation form, see dc_cone_bp).  A view range [v0, v0+nv) may span samples: dc_cone_bp writes the
  * volumes of the samples it meets (for nv = 0, the sample holding view v0, the
  * last one when v0 = n_views) and leaves the others untouched; dc_cone_bp_adjoint
  * reads each view's own sample volume.  dc_plan_create is n_samples = 1. */
@@ -152,7 +153,13 @@ dc_status dc_detector_bp_adjoint(dc_plan plan, const void* GgF, dc_dtype tF, voi
 
 /* Stage 4, eq. 5 with w_d folded: f(x) (+)= sum_{v in range} (D/U)^2 bilinear(gF[v], proj_v(x)).
  * accumulate != 0 adds to f; relu != 0 applies max(., 0) to the result (set it
- * only on the call that completes the view sum, paper Sec. 2.4). */
+ * only on the call that completes the view sum, paper Sec. 2.4).
+ * The plan evaluates each sample's projections (here and in dc_cone_bp_adjoint)
+ * in one of three forms chosen from its geometry: per voxel column when no view's
+ * depth U or detector u coordinate varies along z (detector v axis along z); with
+ * 1/U iterated by a Newton step along z when U changes by at most 2.5e-4 of itself
+ * per voxel step; with a reciprocal per voxel otherwise.  The forms agree to
+ * float32 rounding, and each is deterministic. */
 dc_status dc_cone_bp(dc_plan plan, const void* gF, dc_dtype tF, float* f, int32_t accumulate,
                      int32_t relu, int32_t v0, int32_t nv, hipStream_t stream);
 /* Exact transpose of dc_cone_bp (cone-beam forward projection of Gf):
