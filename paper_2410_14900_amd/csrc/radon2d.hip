@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, To
                                                 const float4* __restrict__ viewf, float scale, int v0, int nv,
                                                 int wl, int tiles_u, int n_tiles) {
   extern __shared__ float2 win[];
-  __shared__ float4 sPar[kKC];   // A, B, t(tile origin) - w0 - 0.5 - wc, kk * wl + wc (int bits)
+  __shared__ float4 sPar[kKC];   // A, B, t(tile origin) - w0 - 0.5 - wc, kk * wl + wc - bits(1.5 2^23) (int bits)
   __shared__ int sW0[kKC];       // first bin of each angle's window
   // XCD-aware order: all tiles of a view run on one XCD (its sinogram stays in one L2)
   const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, To
 #pragma unroll
   for (int h = 0; h < kTPX; ++h) acc[h] = 0.f;
   for (int k0 = 0; k0 < g.n_theta; k0 += kKC) {
-    const int kn = min(kKC, g.n_theta - k0);
+    // uniform: held in a scalar register, so the angle loop costs no vector instructions
+    const int kn = __builtin_amdgcn_readfirstlane(min(kKC, g.n_theta - k0));
     if (threadIdx.x < kn) {
       const int k = k0 + threadIdx.x;
       const double A = angd[3 * k], B = angd[3 * k + 1], C = angd[3 * k + 2];
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, To
       const int w0 = (int)floor(tmin) - 1;
       sW0[threadIdx.x] = w0;
       sPar[threadIdx.x] = make_float4((float)A, (float)B, (float)(t00 - w0 - 0.5 - (wl >> 1)),
-                                      __int_as_float(threadIdx.x * wl + (wl >> 1)));
+                                      __int_as_float((int)((unsigned)(threadIdx.x * wl + (wl >> 1)) - kRoundMagicBits)));
     }
     __syncthreads();
     for (int q = threadIdx.x; q < kn * wl; q += blockDim.x) {
@@ -278,12 +279,12 @@ __global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, To
       // integer t may round one lower, where both intervals give the same value)
       const float th0 = fmaf(fx, P.x, fmaf(fy, P.y, P.z));
       const float b8 = 8.f * P.y;
-      const unsigned bias = kRoundMagicBits - (unsigned)__float_as_int(P.w);
+      const unsigned nbias = (unsigned)__float_as_int(P.w);   // window slot = bits(th + 1.5 2^23) + nbias
 #pragma unroll
       for (int h = 0; h < kTPX; ++h) {
         const float th = fmaf((float)h, b8, th0);
         const float y = th + kRoundMagic;
-        const float2 pr = win[__float_as_uint(y) - bias];
+        const float2 pr = win[__float_as_uint(y) + nbias];
         acc[h] += fmaf(th, pr.y, pr.x);
       }
     }
