@@ -67,10 +67,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (14_001_825_319 + 201_422_079,
+    ("cone_bp_adjoint", "f32"): (13_853_016_130 + 201_421_135,
                                  "ed05dd44992ac7f3e48dbf9e89c35fdee215777108dad7677f1d268b0afd4037"),
-    ("weight_radon", "f32"): (1_073_475_169 + 521_261_371,
-                              "2a75754a52dfd1914756097c5204291663a14a1f89068db2674609ca485e11c5"),
+    ("weight_radon", "f32"): (1_072_506_395 + 521_259_393,
+                              "99bb97b409613206af2df5aa781c93e9b212e68b1bbfdb930b79e11d14a78396"),
 }
 
 
