@@ -174,7 +174,9 @@ dc_status dc_cone_bp_adjoint(dc_plan plan, const float* Gf, const float* f_relu,
  * t = -radius..radius and mirror padding (the edge sample is not repeated) along
  * both axes; views are not mixed.  M, Ms float32 [V][n_theta][n_s]; Ms may alias M.
  * Needs sigma > 0, 1 <= radius <= 255, radius < n_theta and radius < n_s
- * (DC_EINVAL / DC_ESHAPE otherwise) and n_theta + 2 radius <= 992 (DC_ENOTSUP). */
+ * (DC_EINVAL / DC_ESHAPE otherwise), and radius + 1 + 16 (n_theta + 2 radius + 4)
+ * <= 40960 (one workgroup's 160 KiB of LDS; e.g. n_theta <= 2432 at radius 60;
+ * DC_ENOTSUP otherwise). */
 dc_status dc_smooth_weights(dc_plan plan, const float* M, float* Ms, double sigma, int32_t radius,
                             int32_t v0, int32_t nv, hipStream_t stream);
 /* Exact transpose of dc_smooth_weights: GM = G_s^T G_mu^T GMs (the backward of the

@@ -550,8 +550,9 @@ static dc_status check_smooth(const Plan& p, double sigma, int32_t radius) {
     return fail(DC_EINVAL, "radius must be in [1, " + std::to_string(kSmoothMaxRadius) + "]");
   if (radius >= p.grid.n_theta || radius >= p.grid.n_s)
     return fail(DC_ESHAPE, "radius must be below n_theta and n_s (mirror padding)");
-  if (p.grid.n_theta + 2 * radius > 992)
-    return fail(DC_ENOTSUP, "n_theta + 2 radius above 992 (the mu pass stages a column block in 64 KiB of LDS)");
+  if (smooth_mu_lds_bytes(p.grid.n_theta, radius) > kMaxLdsPerBlock)
+    return fail(DC_ENOTSUP, "n_theta + 2 radius too large: the mu pass stages a column block of n_theta + 2 radius "
+                            "rows in one workgroup's LDS (160 KiB)");
   return DC_OK;
 }
 

@@ -112,6 +112,10 @@ struct GaussTaps {
   float w[kSmoothMaxRadius + 1];
 };
 GaussTaps gauss_taps(double sigma, int r);
+// LDS of the smoothing's mu pass (taps and a column block of n_theta + 2r rows);
+// a workgroup may hold up to kMaxLdsPerBlock bytes on gfx950
+size_t smooth_mu_lds_bytes(int n_theta, int r);
+static constexpr size_t kMaxLdsPerBlock = 160 * 1024;
 hipError_t launch_smooth(const Plan& p, const float* in, float* out, double sigma, int r, bool adjoint, int v0,
                          int nv, hipStream_t s);
 

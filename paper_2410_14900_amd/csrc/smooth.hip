@@ -133,6 +133,10 @@ __global__ __launch_bounds__(256) void k_smooth_mu(const float* in, float* out, 
   }
 }
 
+size_t smooth_mu_lds_bytes(int n_theta, int r) {
+  return (size_t)(r + 1 + (n_theta + 2 * r + kOB) * kSmCols) * sizeof(float);
+}
+
 GaussTaps gauss_taps(double sigma, int r) {
   GaussTaps tp{};
   double sum = 0.0;

@@ -145,3 +145,30 @@ def test_wide_shallow_volume_uses_the_clamped_gather(P):
     rhs = float((x.double() * Aty.double()).sum())
     assert abs(lhs - rhs) <= 1e-6 * float(Ax.double().norm() * y.double().norm())
     assert float(Aty.abs().max()) > 0
+
+
+def test_smoothing_on_a_long_angle_axis(P):
+    """The mu pass stages n_theta + 2 radius rows of a column block in one
+    workgroup's LDS: 1200 angles with the paper's radius 60 (1320 rows, above a
+    64 KiB budget) against the oracle, and the first size past 160 KiB rejected."""
+    import dataclasses
+    from oracle import smooth as OS
+    g = synth.Grid(nu=56, nv=48, du=1.0, dv=1.0, n_theta=1200, n_s=synth.radon_bins(56, 48), ds=1.0,   # 74 bins
+                   nx=12, ny=12, nz=10, vx=1.0, vy=1.0, vz=1.0)
+    v = synth.circle_orbit(2, 750.0, 1200.0)
+    plan = P.Plan(g, v)
+    rng = np.random.Generator(np.random.PCG64(4))
+    M = rng.uniform(-1, 0, (2, g.n_theta, g.n_s)).astype(np.float32)
+    Ms = torch.empty((2, g.n_theta, g.n_s), device="cuda")
+    P.dc_smooth_weights(plan, dev(M), Ms, 20.0, 60)
+    assert rel(host(Ms), OS.smooth_weights(M.astype(np.float64), 20.0, 60)) < 1e-5
+    GM = torch.empty_like(Ms)
+    P.dc_smooth_weights_adjoint(plan, dev(M), GM, 20.0, 60)
+    assert rel(host(GM), OS.smooth_weights_adjoint(M.astype(np.float64), 20.0, 60)) < 1e-5
+    # r + 1 + 16 (n_theta + 2 r + 4) floats must fit 40960: at 2433 angles radius 59
+    # fits (40940) and radius 60 does not (40973)
+    big = P.Plan(dataclasses.replace(g, n_theta=2433), v)
+    Mb = torch.zeros((2, 2433, g.n_s), device="cuda")
+    P.dc_smooth_weights(big, Mb, Mb, 20.0, 59)
+    with pytest.raises(P.DcError, match="DC_ENOTSUP"):
+        P.dc_smooth_weights(big, Mb, Mb, 20.0, 60)
