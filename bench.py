@@ -71,10 +71,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_853_016_130 + 201_421_135,
-                                 "ed05dd44992ac7f3e48dbf9e89c35fdee215777108dad7677f1d268b0afd4037"),
-    ("weight_radon", "f32"): (1_072_506_395 + 521_259_393,
-                              "99bb97b409613206af2df5aa781c93e9b212e68b1bbfdb930b79e11d14a78396"),
+    ("cone_bp_adjoint", "f32"): (13_927_214_459 + 201_422_591,
+                                 "b437fbfa6e740ed143ea36cf09fbceed7135dbd07563ec29b555c17090864b38"),
+    ("weight_radon", "f32"): (1_073_162_298 + 521_259_339,
+                              "f1fbf289a81c54b83009e3eae29cdb3f33e462f087ade5cd4ed2bc4cee560f4c"),
 }
 
 
