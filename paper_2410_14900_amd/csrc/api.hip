@@ -246,7 +246,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
                                 std::to_string(kMaxCellTerms) + "); the detector is too coarse for the voxel grid");
   p->cone_max_terms = (int)std::max(1.0, max_cell_terms);
   // largest backprojection block footprint (same box rule as the kernel) ->
-  // how many pixels each of the 256 threads stages per view
+  // how many pixels each of the backprojection's threads stages per view
   {
     const int B[3] = {cone_bp_block(0), cone_bp_block(1), cone_bp_block(2)};
     const int nb[3] = {(g->nx + B[0] - 1) / B[0], (g->ny + B[1] - 1) / B[1], (g->nz + B[2] - 1) / B[2]};
@@ -273,7 +273,7 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
             worst = std::max(worst, w * h);
           }
     }
-    const int need = (int)std::ceil(worst / 256.0);
+    const int need = (int)std::ceil(worst / (double)cone_bp_threads());
     p->bp_stage = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 0;
     // Form of the cone kernels, decided per sample (so a batched plan computes what
     // each scan's own plan does).  den = U/D and num_u free of z on every view: a

@@ -7,7 +7,7 @@
 // with the per-view projective map i* = num_u/den, j* = num_v/den, den = U/D,
 // all affine in the voxel index (float64 table built by the plan).
 //
-// Backprojection work mapping: a workgroup owns a 16 x 16 x 8 voxel block and a
+// Backprojection work mapping: a workgroup owns a 16 x 32 x 8 voxel block and a
 // thread one (x, y) column segment of 8 voxels, walked in z (8 rather than 16
 // keeps the kernel at 3 waves per SIMD; measured 4% faster); lanes of a wave
 // cover 16 consecutive x of 4 rows, so volume writes are 64-byte segments.  Per view, the block's
@@ -24,7 +24,8 @@
 
 namespace dc {
 
-static constexpr int kBX = 16, kBY = 16, kZC = 8;
+static constexpr int kBX = 16, kBY = 32, kZC = 8;
+static constexpr int kBPThreads = kBX * kBY;   // 512
 static constexpr float kRoundMagic = 12582912.0f;         // 1.5 * 2^23
 static constexpr unsigned kRoundMagicBits = 0x4B400000u;  // its bit pattern
 
@@ -144,10 +145,10 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
 // holds the largest footprint); STAGE == 0 selects direct global taps.  FORM
 // (staged form only) is the plan's choice for the sample (ConeForm).
 template <typename T, int STAGE, int FORM>
-__global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
+__global__ __launch_bounds__(kBPThreads) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
                                                  int nv, const int* __restrict__ first, int s_lo, int nzb) {
-  constexpr int kTile = STAGE > 0 ? 256 * STAGE : 1;
+  constexpr int kTile = STAGE > 0 ? kBPThreads * STAGE : 1;
   __shared__ float tile[2][kTile];
   const int tid = threadIdx.y * kBX + threadIdx.x;
   // grid z = (sample, z-block): this workgroup sums the views of its sample that
@@ -198,12 +199,12 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
       const __amdgpu_buffer_rsrc_t im =
           __builtin_amdgcn_make_buffer_rsrc((void*)(gF + (size_t)v * npix), (short)0, (int)img_bytes, kBufferWord3);
       // row = floor((e + 1/2) / w): the quotient lies at least 1/(2w) from an
-      // integer, while the hardware reciprocal's error stays below 1e-3/w for e < 4096
+      // integer, while the hardware reciprocal's error stays below 2e-3/w for e < 8192
       const float rw = __builtin_amdgcn_rcpf((float)b.w);
       const int n = b.w * b.h;
 #pragma unroll
       for (int s = 0; s < STAGE; ++s) {
-        const int e = tid + 256 * s;
+        const int e = tid + kBPThreads * s;
         const int row = (int)(((float)e + 0.5f) * rw);
         const int ii = b.i_lo + (e - __mul24(row, b.w)), jj = b.j_lo + row;
         const bool in = e < n && (unsigned)ii < (unsigned)g.nu && (unsigned)jj < (unsigned)g.nv;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(256) void k_cone_bp(const T* __restrict__ gF, float
     // until the barrier that ends the current view
     auto store_stage = [&](int buf) {
 #pragma unroll
-      for (int s = 0; s < STAGE; ++s) tile[buf][tid + 256 * s] = to_f32(stg[s]);
+      for (int s = 0; s < STAGE; ++s) tile[buf][tid + kBPThreads * s] = to_f32(stg[s]);
     };
     // Footprints are computed by one wave per view, two views ahead, and passed
     // on in a two-slot LDS ring: the box of view v sits in slot (v - v0) & 1 from
@@ -757,6 +758,7 @@ static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF,
 }
 
 int cone_bp_block(int axis) { return axis == 0 ? kBX : axis == 1 ? kBY : kZC; }
+int cone_bp_threads() { return kBPThreads; }
 
 hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, void* GgF, dc_dtype tF, int v0,
                           int nv, hipStream_t s) {

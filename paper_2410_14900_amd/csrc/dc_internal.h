@@ -99,6 +99,7 @@ void set_error(const std::string& msg);
 
 // backprojection voxel block edge along axis 0/1/2 (cone.hip)
 int cone_bp_block(int axis);
+int cone_bp_threads();   // threads per backprojection workgroup
 // pixel tile of the detector-BP (interpolation) kernel along u (axis 0) and v (axis 1)
 int interp_tile(int axis);
 

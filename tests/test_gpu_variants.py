@@ -1,9 +1,9 @@
 """GPU parity for code paths that the ordinary test geometries never reach.
 
 - Cone backprojection (eq. 11, A3d^T): a plan stages each view's detector
-  footprint of a 16x16x8 voxel block in LDS, sized from the largest footprint
+  footprint of a 16x32x8 voxel block in LDS, sized from the largest footprint
   over all blocks and views.  The classes are 4, 8, 12 and 16 pixels per thread
-  of 256, and direct global taps beyond that.  Ordinary geometries all fall in
+  of 512, and direct global taps beyond that.  Ordinary geometries all fall in
   the first class.  Finer detectors here force each of the others, and
   `footprint_class` checks on the host that they do.
 - Splat (the 2D Radon transform of eqs. 7, 8): when the sinogram rows are
@@ -46,7 +46,8 @@ def host(t):
     return t.detach().float().cpu().numpy().astype(np.float64)
 
 
-BLOCK = (16, 16, 8)   # voxels per backprojection workgroup along x, y, z
+BLOCK = (16, 32, 8)   # voxels per backprojection workgroup along x, y, z
+THREADS = 512         # threads per backprojection workgroup (one per x, y column)
 
 
 def footprint_class(g, views):
@@ -65,7 +66,7 @@ def footprint_class(g, views):
                     w = math.floor(bi.max()) - math.floor(bi.min()) + 5
                     h = math.floor(bj.max()) - math.floor(bj.min()) + 5
                     worst = max(worst, w * h)
-    need = math.ceil(worst / 256)
+    need = math.ceil(worst / THREADS)
     return next((c for c in (4, 8, 12, 16) if need <= c), 0)
 
 
@@ -77,7 +78,7 @@ def fine_detector(du):
     return g, synth.sinusoid_orbit(3, 750.0, 1200.0)
 
 
-STAGING = {8: 0.6, 12: 0.5, 16: 0.4, 0: 0.3}   # class -> detector pitch that forces it
+STAGING = {8: 0.45, 12: 0.32, 16: 0.25, 0: 0.2}   # class -> detector pitch that forces it
 
 
 @pytest.mark.parametrize("cls", list(STAGING))
