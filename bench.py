@@ -71,10 +71,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_927_214_459 + 201_422_591,
-                                 "b437fbfa6e740ed143ea36cf09fbceed7135dbd07563ec29b555c17090864b38"),
-    ("weight_radon", "f32"): (1_073_162_298 + 521_259_339,
-                              "f1fbf289a81c54b83009e3eae29cdb3f33e462f087ade5cd4ed2bc4cee560f4c"),
+    ("cone_bp_adjoint", "f32"): (13_903_691_404 + 201_422_399,
+                                 "93fe76bc13d75f123fc33fa7d80cd39cfe186f3e2b24dd9ae4966881990dc0c5"),
+    ("weight_radon", "f32"): (1_070_997_085 + 521_261_235,
+                              "e789fe751c643842aea2ed3f070821977d7efe2816d4ced635a142114f392725"),
 }
 
 
