@@ -146,7 +146,8 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
     if (w > wl) wl = w;
   }
   p->interp_wl = wl;
-  if (wl > 256) return fail(DC_ENOTSUP, "detector pitch too coarse for the s-bin width (ds << du)");
+  // the window rows of a chunk of 32 angles take 32 wl 8 bytes of LDS (<= 128 KiB)
+  if (wl > 512) return fail(DC_ENOTSUP, "detector pitch too coarse for the s-bin width (ds << du)");
 
   // Radon work list: runs of angles whose pixels spread fastest along rows
   // (|A| >= |B|, lanes walk i) or along columns (lanes walk j), cut into chunks.

@@ -208,25 +208,27 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
 }
 
 // ----------------------------------------------------------------- interp
-// One workgroup owns a 32 x 64 pixel tile of one view (256 threads, 8 pixels
-// each, 8 rows apart: the per-angle set-up is shared by 8 taps; 11% faster than
-// 32 x 32).  Angles are processed in chunks of 32: for each angle the
+// One workgroup owns a 64 x 64 pixel tile of one view (512 threads, 8 pixels
+// each, 8 rows apart: the per-angle set-up is shared by 8 taps; 8% faster than
+// 32 x 64, itself 11% faster than 32 x 32: a wider tile shares each angle's
+// window staging over more pixels).  Angles are processed in chunks of 32: for each angle the
 // tile's s-range (plus margins) of the row is staged in LDS as one (c, s) pair per
 // bin interval e, the line through its two samples written about the window's
 // centre wc: value(th) = c + s th with th = t - 0.5 - wc measured from that centre.
 // A linear-interpolation tap is then one 8-byte LDS read and one FMA on th itself
 // (no fraction to form).  The form cancels at most |th| <= wl/2 times the slope's
-// rounding: 2.7e-6 relative against the float64 oracle on the benchmark grid
-// (1.6e-6 with 32 x 32 tiles, as for the midpoint form).  Tile-local positions
-// are derived from float64 per-(tile, angle) offsets, which keeps them below
-// ~75 bins and their float32 rounding below 5e-6 bins.
-static constexpr int kTX = 32, kTY = 64, kKC = 32;
+// rounding: 3.2e-6 relative against the float64 oracle on the benchmark grid
+// (2.7e-6 with 32 x 64 tiles, 1.6e-6 with 32 x 32).  Tile-local positions are
+// derived from float64 per-(tile, angle) offsets, which keeps them below ~95
+// bins and their float32 rounding below 6e-6 bins.
+static constexpr int kTX = 64, kTY = 64, kKC = 32;
+static constexpr int kIPThreads = kTX * 8;   // 512: 8 row groups
 static constexpr int kTPX = kTY / 8;   // pixels per thread (rows 8 apart)
 
 int interp_tile(int axis) { return axis == 0 ? kTX : kTY; }
 
 template <typename Tin, typename Tout, bool WCOS>
-__global__ __launch_bounds__(256) void k_interp(const Tin* __restrict__ rows, Tout* __restrict__ out, KGrid g,
+__global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ rows, Tout* __restrict__ out, KGrid g,
                                                 const double* __restrict__ angd,
                                                 const float4* __restrict__ viewf, float scale, int v0, int nv,
                                                 int wl, int tiles_u, int n_tiles) {
@@ -354,11 +356,11 @@ hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wc
     return by_dtype(t_out, [&](auto tout) {
       using Tout = decltype(tout);
       if (wcos)
-        hipLaunchKernelGGL((k_interp<Tin, Tout, true>), grid, dim3(256), lds, s, (const Tin*)rows, (Tout*)out,
+        hipLaunchKernelGGL((k_interp<Tin, Tout, true>), grid, dim3(kIPThreads), lds, s, (const Tin*)rows, (Tout*)out,
                            p.kg, p.d_ang, (const float4*)p.d_view, scale, v0,
                            nv, p.interp_wl, tiles_u, n_tiles);
       else
-        hipLaunchKernelGGL((k_interp<Tin, Tout, false>), grid, dim3(256), lds, s, (const Tin*)rows, (Tout*)out,
+        hipLaunchKernelGGL((k_interp<Tin, Tout, false>), grid, dim3(kIPThreads), lds, s, (const Tin*)rows, (Tout*)out,
                            p.kg, p.d_ang, (const float4*)p.d_view, scale, v0,
                            nv, p.interp_wl, tiles_u, n_tiles);
       return hipGetLastError();
