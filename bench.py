@@ -71,10 +71,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_903_691_404 + 201_422_399,
+    ("cone_bp_adjoint", "f32"): (13_962_975_281 + 201_420_895,
                                  "93fe76bc13d75f123fc33fa7d80cd39cfe186f3e2b24dd9ae4966881990dc0c5"),
-    ("weight_radon", "f32"): (1_070_997_085 + 521_261_235,
-                              "e789fe751c643842aea2ed3f070821977d7efe2816d4ced635a142114f392725"),
+    ("weight_radon", "f32"): (1_072_313_956 + 521_261_375,
+                              "83c4b9a057877df0360251fe1f0ff26998c99361a5354acbecc3532bd45d56e7"),
 }
 
 
