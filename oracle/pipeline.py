@@ -225,11 +225,24 @@ def cone_bp_literal(gF_unweighted, grid, views):
 
 
 # ------------------------------------------------------------- transposes
-def cone_bp_adjoint(Gf, grid, views, relu_f=None):
+def voxel_centres(grid, idx):
+    """World positions of the voxels with indices idx[n] = (iz, iy, ix), placed
+    as in ``voxel_points``."""
+    idx = np.asarray(idx)
+    return np.stack([(idx[:, 2] - (grid.nx - 1) / 2.0) * grid.vx + grid.ox,
+                     (idx[:, 1] - (grid.ny - 1) / 2.0) * grid.vy + grid.oy,
+                     (idx[:, 0] - (grid.nz - 1) / 2.0) * grid.vz + grid.oz], axis=-1)
+
+
+def cone_bp_adjoint(Gf, grid, views, relu_f=None, support=None):
     """Exact transpose of ``cone_bp``: every voxel spreads (D/U)^2 Gf(x) over
     its four bilinear taps.  ``relu_f`` applies the ReLU derivative mask
-    [f > 0] to Gf first."""
-    P = voxel_points(grid)
+    [f > 0] to Gf first.
+
+    ``support`` (optional): indices (iz, iy, ix) [n, 3] of the only voxels where
+    Gf may be nonzero; Gf (and relu_f) then hold their n values, and the sum runs
+    over those voxels alone (the terms of every other voxel are zero)."""
+    P = voxel_points(grid) if support is None else voxel_centres(grid, support)
     G = np.asarray(Gf, np.float64)
     if relu_f is not None:
         G = G * (np.asarray(relu_f) > 0)

@@ -250,10 +250,17 @@ __global__ __launch_bounds__(kBPThreads) void k_cone_bp(const T* __restrict__ gF
       }
       if (v + 2 < v0 + nv && wave == ((v - v0) & 3)) publish(v + 2, buf);
       const float* t = tile[buf];
-      // Tap indices need no clamping: every voxel of the block projects inside the
-      // convex hull of its corners' projections, and the staged box extends that
-      // hull by at least one pixel on each side (float rounding of the corners and
-      // of the per-voxel walk is below 1e-4 pixel).
+      // Tap indices of voxels inside the volume need no clamping: every voxel of the
+      // block's box [bx0, bx1] x [by0, by1] x [bz0, bz1] projects inside the convex
+      // hull of its corners' projections, and the staged box extends that hull by
+      // at least one pixel on each side (float rounding of the corners and of the
+      // per-voxel walk is below 1e-4 pixel).  Padding lanes and slices (ix > bx1,
+      // iy > by1 or iz > bz1 when a volume side is not a multiple of the block)
+      // form taps from points outside that box, sometimes behind the source
+      // (den <= 0), so their LDS addresses can leave the tile or the workgroup's
+      // LDS.  Nothing depends on those reads: LDS loads never fault (past the
+      // allocation they return 0, inside it any value), and the results of those
+      // lanes and slices are never written (the guards at the end).
       if constexpr (FORM == kConeZinv) {
         const ColumnMapZ c = column_map_z(proj + 12 * v, ix, iy, iz0);
         const float* tc = t + (c.i - cur.i_lo);

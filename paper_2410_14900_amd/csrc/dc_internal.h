@@ -93,6 +93,7 @@ struct Plan {
   int splat_max_terms = 0;       // max pixels that share one (angle, bin)
   int splat_checked = 1;         // 0 when every pixel lands on bins [-1, n_s) for all angles
   int interp_wl = 0;             // LDS window length for the interpolating kernels
+                                 // (above kInterpLocalAbove: the midpoint-local tap form)
 };
 
 void set_error(const std::string& msg);
@@ -102,6 +103,7 @@ int cone_bp_block(int axis);
 int cone_bp_threads();   // threads per backprojection workgroup
 // pixel tile of the detector-BP (interpolation) kernel along u (axis 0) and v (axis 1)
 int interp_tile(int axis);
+static constexpr int kInterpLocalAbove = 160;
 
 // samples whose views meet [v0, v0+nv): s_lo..s_hi; for an empty range the
 // sample holding view v0 (the last one when v0 = V)

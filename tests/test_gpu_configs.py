@@ -127,3 +127,144 @@ def test_c5_fp16_storage_with_recomputed_radon_stack(P):
     ref = O.cone_bp(gF.float().cpu().numpy(), grid, views, points=pts)
     got = f.cpu().numpy()[idx[:, 0], idx[:, 1], idx[:, 2]]
     assert rel(got, ref) < 1e-5
+
+
+# --------------------------------------------------------- against the oracle
+def _host(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def _urand(shape, seed, lo=-1.0, hi=1.0, dtype=torch.float32):
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    return (torch.rand(shape, device="cuda", generator=gen, dtype=torch.float32) * (hi - lo) + lo).to(dtype)
+
+
+def _support(grid, frac, seed):
+    """Distinct random voxel indices (iz, iy, ix), about frac of the volume."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(frac * grid.nx * grid.ny * grid.nz)
+    flat = np.unique(rng.integers(0, grid.nx * grid.ny * grid.nz, n))
+    iz, rem = np.divmod(flat, grid.nx * grid.ny)
+    iy, ix = np.divmod(rem, grid.nx)
+    return np.stack([iz, iy, ix], axis=1), torch.as_tensor(flat, device="cuda")
+
+
+C3_VIEWS = [0, 99, 100, 459]   # both ends of the arc, first and last circle view
+
+
+def test_c3_gradient_on_sampled_views_against_the_oracle(P):
+    """dL/dM at full C3 size (all 460 views, ReLU on) against the oracle's chain of
+    transposes on views at both ends of the arc and of the circle, fed the GPU's
+    dL/df and ReLU output.  The loss is the squared error over a random 2 % of
+    the voxels (spread over the whole volume), so dL/df is zero elsewhere and the
+    oracle's cone transpose sums over those voxels only (the same sum)."""
+    grid, views, g, target = scan("C3")
+    V = len(views)
+    print("\n[gpu configs] C3 dL/dM vs oracle, views", C3_VIEWS, flush=True)
+    plan = P.Plan(grid, views)
+    gen = torch.Generator(device="cuda").manual_seed(33)
+    M0 = 0.4 + 0.2 * torch.rand((V,) + plan.sino_shape, device="cuda", generator=gen)
+    idx, flat = _support(grid, 0.02, 34)
+    mask = torch.zeros(grid.nx * grid.ny * grid.nz, device="cuda")
+    mask[flat] = 1.0
+    mask = mask.view(plan.vol_shape)
+    M = M0.clone().requires_grad_(True)
+    f = P.reconstruct(plan, M, g=g, relu=True)
+    Gf = (f.detach() - target) * mask
+    f.backward(Gf)
+    got = M.grad
+    sel = (idx[:, 0], idx[:, 1], idx[:, 2])
+    Gf_s = _host(Gf)[sel]
+    f_s = _host(f)[sel]
+    for v in C3_VIEWS:
+        one = views.subset([v])
+        GgF = O.cone_bp_adjoint(Gf_s, grid, one, relu_f=f_s, support=idx)
+        GH = O.detector_bp_adjoint(GgF, grid)
+        R = O.weight_radon(_host(g[v:v + 1]), grid, one)
+        GM, _ = O.filter_stack_adjoint(GH, R, _host(M0[v:v + 1]), grid, one)
+        e = rel(_host(got[v]), GM[0])
+        print("[gpu configs] C3 view %d: dL/dM rel-L2 %.2e" % (v, e), flush=True)
+        assert e < 1e-4
+
+
+C5_VIEWS = [0, 495]
+
+
+@pytest.fixture(scope="module")
+def c5(P):
+    grid, views = synth.config_geometry("C5")
+    print("\n[gpu configs] C5 stages vs oracle", grid.as_dict(), "views", len(views), flush=True)
+    return grid, views, P.Plan(grid, views)
+
+
+def _per_view(gpu, ref, views_idx):
+    return [rel(_host(gpu[v]), ref[i]) for i, v in enumerate(views_idx)]
+
+
+@pytest.mark.timeout(600)
+def test_c5_weight_radon_on_sampled_views(P, c5):
+    """The splat at 1381 bins, 7 angles per workgroup, 976^2 detector."""
+    grid, views, plan = c5
+    V = len(views)
+    x = _urand((V, grid.nv, grid.nu), 51, 0.0, 1.0)
+    R = torch.empty((V, grid.n_theta, grid.n_s), device="cuda")
+    P.dc_weight_radon(plan, x, R)
+    ref = O.weight_radon(_host(x[C5_VIEWS]), grid, views.subset(C5_VIEWS))
+    errs = _per_view(R, ref, C5_VIEWS)
+    print("[gpu configs] C5 weight_radon rel-L2", errs, flush=True)
+    assert max(errs) < 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_c5_detector_bp_fp16_on_sampled_views(P, c5):
+    """The interp on the 0.308 mm grid, FP16 sinogram in and FP16 image out (the
+    C5 storage): against the oracle on the same FP16 inputs; the output's one
+    FP16 rounding (2^-11 relative) sets the bar."""
+    grid, views, plan = c5
+    V = len(views)
+    H = _urand((V, grid.n_theta, grid.n_s), 52, dtype=torch.float16)
+    gF = torch.empty((V, grid.nv, grid.nu), device="cuda", dtype=torch.float16)
+    P.dc_detector_bp(plan, H, gF)
+    ref = O.detector_bp(_host(H[C5_VIEWS]), grid)
+    errs = _per_view(gF, ref, C5_VIEWS)
+    print("[gpu configs] C5 detector_bp (fp16) rel-L2", errs, flush=True)
+    assert max(errs) < 1e-3
+
+
+@pytest.mark.timeout(600)
+def test_c5_detector_bp_adjoint_fp16_on_sampled_views(P, c5):
+    """The detector Radon (splat) with FP16 storage in and out."""
+    grid, views, plan = c5
+    V = len(views)
+    GgF = _urand((V, grid.nv, grid.nu), 53, dtype=torch.float16)
+    GH = torch.empty((V, grid.n_theta, grid.n_s), device="cuda", dtype=torch.float16)
+    P.dc_detector_bp_adjoint(plan, GgF, GH)
+    ref = O.detector_bp_adjoint(_host(GgF[C5_VIEWS]), grid)
+    errs = _per_view(GH, ref, C5_VIEWS)
+    print("[gpu configs] C5 detector_bp_adjoint (fp16) rel-L2", errs, flush=True)
+    assert max(errs) < 1e-3
+
+
+@pytest.mark.timeout(600)
+def test_c5_cone_bp_adjoint_on_sampled_views(P, c5):
+    """The cone FP at 512^3 / 976^2, with the ReLU mask, FP32 and FP16 output.
+    Gf is nonzero on a random 0.5 % of the voxels (670k, spread over the whole
+    volume), so the oracle sums over those voxels only; the GPU gathers over
+    the full volume as always."""
+    grid, views, plan = c5
+    V = len(views)
+    idx, flat = _support(grid, 0.005, 54)
+    vals = _urand((len(flat),), 55)
+    frl = _urand((len(flat),), 56)
+    Gf = torch.zeros(grid.nx * grid.ny * grid.nz, device="cuda")
+    Gf[flat] = vals
+    fr = torch.zeros_like(Gf)
+    fr[flat] = frl
+    Gf, fr = Gf.view(plan.vol_shape), fr.view(plan.vol_shape)
+    ref = O.cone_bp_adjoint(_host(vals), grid, views.subset(C5_VIEWS), relu_f=_host(frl), support=idx)
+    for dt, tol in ((torch.float32, 1e-5), (torch.float16, 1e-3)):
+        GgF = torch.empty((V, grid.nv, grid.nu), device="cuda", dtype=dt)
+        P.dc_cone_bp_adjoint(plan, Gf, GgF, f_relu=fr)
+        errs = _per_view(GgF, ref, C5_VIEWS)
+        print("[gpu configs] C5 cone_bp_adjoint", dt, "rel-L2", errs, flush=True)
+        assert max(errs) < tol

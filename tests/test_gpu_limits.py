@@ -167,8 +167,45 @@ def test_smoothing_on_a_long_angle_axis(P):
     assert rel(host(GM), OS.smooth_weights_adjoint(M.astype(np.float64), 20.0, 60)) < 1e-5
     # r + 1 + 16 (n_theta + 2 r + 4) floats must fit 40960: at 2433 angles radius 59
     # fits (40940) and radius 60 does not (40973)
+    # at the bound itself the staged column block fills the LDS: a seeded nonzero
+    # weight and its transpose against the oracle there
     big = P.Plan(dataclasses.replace(g, n_theta=2433), v)
-    Mb = torch.zeros((2, 2433, g.n_s), device="cuda")
-    P.dc_smooth_weights(big, Mb, Mb, 20.0, 59)
+    Mb = rng.uniform(-1, 0, (2, 2433, g.n_s)).astype(np.float32)
+    Mbs = torch.empty((2, 2433, g.n_s), device="cuda")
+    P.dc_smooth_weights(big, dev(Mb), Mbs, 20.0, 59)
+    assert rel(host(Mbs), OS.smooth_weights(Mb.astype(np.float64), 20.0, 59)) < 1e-5
+    GMb = torch.empty_like(Mbs)
+    P.dc_smooth_weights_adjoint(big, dev(Mb), GMb, 20.0, 59)
+    assert rel(host(GMb), OS.smooth_weights_adjoint(Mb.astype(np.float64), 20.0, 59)) < 1e-5
     with pytest.raises(P.DcError, match="DC_ENOTSUP"):
-        P.dc_smooth_weights(big, Mb, Mb, 20.0, 60)
+        P.dc_smooth_weights(big, Mbs, Mbs, 20.0, 60)
+
+
+def test_detector_bp_on_bins_five_times_finer_than_pixels(P):
+    """Bins of a fifth of the pixel pitch make the detector BP's LDS window 450
+    intervals wide (the 512 cap is 128 KiB for 32 angles); such windows take the
+    midpoint-local tap form, whose rounding does not grow with the window.  The
+    detector BP and the weighted Radon's transpose (both interpolating), and the
+    two splats, against the oracle at the float32 bar."""
+    g = synth.Grid(nu=64, nv=48, du=1.0, dv=1.0, n_theta=24, n_s=400, ds=0.2,
+                   nx=12, ny=12, nz=10, vx=1.0, vy=1.0, vz=1.0)
+    views = synth.sinusoid_orbit(3, 750.0, 1200.0)
+    plan = P.Plan(g, views)
+    rng = np.random.Generator(np.random.PCG64(8))
+    V = len(views)
+    H = rng.uniform(-1, 1, (V, g.n_theta, g.n_s)).astype(np.float32)
+    gF = torch.empty((V, g.nv, g.nu), device="cuda")
+    P.dc_detector_bp(plan, dev(H), gF)
+    e1 = rel(host(gF), O.detector_bp(H.astype(np.float64), g))
+    Gg = torch.empty((V, g.nv, g.nu), device="cuda")
+    P.dc_weight_radon_adjoint(plan, dev(H), Gg)
+    e2 = rel(host(Gg), O.weight_radon_adjoint(H.astype(np.float64), g, views))
+    x = rng.uniform(-1, 1, (V, g.nv, g.nu)).astype(np.float32)
+    R = torch.empty((V, g.n_theta, g.n_s), device="cuda")
+    P.dc_weight_radon(plan, dev(x), R)
+    e3 = rel(host(R), O.weight_radon(x.astype(np.float64), g, views))
+    P.dc_detector_bp_adjoint(plan, dev(x), R)
+    e4 = rel(host(R), O.detector_bp_adjoint(x.astype(np.float64), g))
+    print("\n[gpu limits] ds = du/5: detector_bp %.2e, weight_radon_adjoint %.2e, weight_radon %.2e, "
+          "detector_bp_adjoint %.2e" % (e1, e2, e3, e4), flush=True)
+    assert max(e1, e2, e3, e4) < 1e-5

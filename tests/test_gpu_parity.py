@@ -270,7 +270,10 @@ def test_reconstruction_end_to_end(P, case, store):
     assert rel(host(f), ref) < (TOL32 if store == "f32" else TOL_BF16)
 
 
-def test_gradient_wrt_M(P, case):
+@pytest.mark.parametrize("recompute_R", [False, True])
+def test_gradient_wrt_M(P, case, recompute_R):
+    """dL/dM against the oracle's chain of transposes; with recompute_R the
+    backward rebuilds the Radon stack from g instead of keeping it."""
     name, g, views, plan = case
     V = len(views)
     gp, ell = _projections(g, views)
@@ -278,7 +281,7 @@ def test_gradient_wrt_M(P, case):
     M = rng.uniform(0.3, 0.7, (V, g.n_theta, g.n_s)).astype(np.float32)
     target = rng.uniform(0, 1e-3, (g.nz, g.ny, g.nx)).astype(np.float32)
     Mt = dev(M).requires_grad_(True)
-    f = P.reconstruct(plan, Mt, g=dev(gp))
+    f = P.reconstruct(plan, Mt, g=dev(gp), recompute_R=recompute_R)
     loss = 0.5 * ((f - dev(target)) ** 2).sum()
     loss.backward()
     Gf = O.reconstruct(gp.astype(np.float64), M.astype(np.float64), g, views) - target
@@ -286,7 +289,7 @@ def test_gradient_wrt_M(P, case):
     assert rel(host(Mt.grad), ref) < TOL_GRAD
     # the layer form gives the same bits
     M2 = dev(M).requires_grad_(True)
-    f2 = P.DCFBP(plan).apply(dev(gp), M2)
+    f2 = P.DCFBP(plan, recompute_R=recompute_R).apply(dev(gp), M2)
     (0.5 * ((f2 - dev(target)) ** 2).sum()).backward()
     assert torch.equal(f2, f) and torch.equal(M2.grad, Mt.grad)
 

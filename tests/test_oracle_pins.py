@@ -423,3 +423,19 @@ def test_orbit_frames(orbit):
     if orbit in ("circle", "sinusoid"):     # closed: tangent ~ central difference of positions
         cd = 0.5 * (np.roll(views.src, -1, 0) - np.roll(views.src, 1, 0))
         assert rel(cd, views.tangent) < 1e-2   # central difference is off by ~dlam^2/6
+
+
+def test_cone_adjoint_restricted_to_a_support_is_the_dense_sum():
+    """The support form of the cone transpose (used where the full volume is too
+    large for the oracle) sums the same terms as the dense form of a volume that
+    is zero off the support, with the ReLU mask applied to the same values."""
+    g, views = synth.config_geometry("C1", n_views=5)
+    r = np.random.Generator(np.random.PCG64(1))
+    idx = np.unique(np.stack([r.integers(0, n, 300) for n in (g.nz, g.ny, g.nx)], 1), axis=0)
+    vals, fr = r.normal(size=len(idx)), r.normal(size=len(idx))
+    Gf, F = np.zeros((g.nz, g.ny, g.nx)), np.zeros((g.nz, g.ny, g.nx))
+    Gf[idx[:, 0], idx[:, 1], idx[:, 2]] = vals
+    F[idx[:, 0], idx[:, 1], idx[:, 2]] = fr
+    dense = P.cone_bp_adjoint(Gf, g, views, relu_f=F)
+    np.testing.assert_allclose(P.cone_bp_adjoint(vals, g, views, relu_f=fr, support=idx), dense,
+                               rtol=1e-13, atol=1e-13 * np.abs(dense).max())
