@@ -118,6 +118,35 @@ dc_status dc_plan_create_batched(const dc_grid* grid, const dc_view* views, int3
                                  const int32_t* first_view, int32_t n_samples, uint32_t flags,
                                  dc_plan* out);
 dc_status dc_plan_destroy(dc_plan plan);
+
+/* The bounds and kernel forms a plan over these views would use, computed on the
+ * host only (no device, no allocation): the same float64 derivation as
+ * dc_plan_create, for a one-scan plan.  They decide the safety and accuracy of
+ * the fixed-point stages (dc_weight_radon and dc_detector_bp_adjoint accumulate
+ * pixel terms per (angle, bin); dc_cone_bp_adjoint voxel terms per detector cell):
+ * each term is rounded to an integer number of units, the largest term of a view
+ * (splat: max |w_cos g| or |GgF| over the view's pixels) or of the call (cone FP:
+ * max |Gf| times the view's bound on (D/U)^2) taking qmax units, and a sum of at
+ * most max_terms such integers never leaves 32 bits.  So every output's absolute
+ * error is at most (number of terms it sums) x 1/2 unit, relative to that
+ * largest term: the stages are exact transposes up to this rounding, which is
+ * small against large outputs but not against outputs far below the largest
+ * term.  Returns DC_OK, or the dc_validate / dc_plan_create status and message. */
+typedef struct {
+  int32_t splat_angles;      /* sinogram rows one splat workgroup holds in LDS */
+  int32_t splat_max_terms;   /* bound on the pixels whose bin floor(t) is one bin, on one angle */
+  int32_t splat_checked;     /* 1 if a pixel may fall outside bins [-1, n_s): the range-checked splat */
+  int32_t interp_window;     /* detector-BP window: sinogram intervals staged per angle and pixel tile */
+  int32_t interp_local;      /* 1 if that window takes the midpoint-local tap form (wide windows) */
+  int32_t cone_max_terms;    /* bound on the voxel centres projecting into one detector cell of one view */
+  int32_t bp_stage;          /* detector pixels each cone-BP thread stages per view (0: taps from memory) */
+  int32_t cone_form;         /* 0: reciprocal per voxel, 1: Newton step along z, 2: z-invariant columns */
+  int32_t bp_block[3];       /* cone-BP voxel block (x, y, z) */
+  int32_t interp_tile[2];    /* detector-BP pixel tile (u, v) */
+  float   splat_qmax;        /* units of the largest splat term */
+  float   cone_qmax;         /* units of the largest cone-FP term */
+} dc_bounds;
+dc_status dc_plan_bounds(const dc_grid* grid, const dc_view* views, int32_t n_views, dc_bounds* out);
 /* Thread-local text of the last error (empty string if none). */
 const char* dc_last_error(void);
 /* Size queries used by bindings: views, samples, and the grid the plan was built with. */

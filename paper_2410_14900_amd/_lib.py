@@ -42,6 +42,13 @@ class DcOrbitSegment(ctypes.Structure):
 DC_SEG_CIRCLE, DC_SEG_ARC, DC_SEG_LINE, DC_SEG_SINUSOID = 1, 2, 3, 4
 
 
+class DcBounds(ctypes.Structure):
+    _fields_ = [("splat_angles", c_int32), ("splat_max_terms", c_int32), ("splat_checked", c_int32),
+                ("interp_window", c_int32), ("interp_local", c_int32), ("cone_max_terms", c_int32),
+                ("bp_stage", c_int32), ("cone_form", c_int32), ("bp_block", c_int32 * 3),
+                ("interp_tile", c_int32 * 2), ("splat_qmax", c_float), ("cone_qmax", c_float)]
+
+
 class DcError(RuntimeError):
     def __init__(self, status, where, msg):
         self.status = status
@@ -56,6 +63,7 @@ SIGNATURES = {
     "dc_plan_create_batched": (_i, [POINTER(DcGrid), POINTER(DcView), _i, POINTER(c_int32), _i, c_uint32,
                                    POINTER(c_void_p)]),
     "dc_plan_destroy": (_i, [_p]),
+    "dc_plan_bounds": (_i, [POINTER(DcGrid), POINTER(DcView), _i, POINTER(DcBounds)]),
     "dc_last_error": (c_char_p, []),
     "dc_plan_n_views": (_i, [_p]),
     "dc_plan_n_samples": (_i, [_p]),

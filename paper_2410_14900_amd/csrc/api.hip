@@ -20,103 +20,21 @@ static dc_status fail(dc_status st, const std::string& msg) {
   return st;
 }
 
-static inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
-static inline void cross3(const double* a, const double* b, double* o) {
-  o[0] = a[1] * b[2] - a[2] * b[1];
-  o[1] = a[2] * b[0] - a[0] * b[2];
-  o[2] = a[0] * b[1] - a[1] * b[0];
-}
-
 static dc_status validate(const dc_grid* g, const dc_view* views, int32_t n) {
-  if (!g || !views) return fail(DC_EINVAL, "null grid or views");
-  if (n < 1) return fail(DC_ESHAPE, "n_views must be >= 1");
-  if (g->nu < 1 || g->nv < 1 || g->n_theta < 1 || g->n_s < 2 || g->nx < 1 || g->ny < 1 || g->nz < 1)
-    return fail(DC_ESHAPE, "grid sizes must be positive (n_s >= 2)");
-  const double lim = 2147483647.0;
-  if ((double)g->nu * g->nv > lim / 4 || (double)g->n_theta * g->n_s > lim / 4 ||
-      (double)g->nx * g->ny * g->nz > lim / 4)
-    return fail(DC_ESHAPE, "per-view image, sinogram or volume too large for 32-bit indexing");
-  if (g->n_s > 4096) return fail(DC_ESHAPE, "n_s above 4096 not supported (sinogram rows are staged in LDS)");
-  if (g->nz > 1024) return fail(DC_ESHAPE, "nz above 1024 not supported");
-  if (!(g->du > 0 && g->dv > 0 && g->ds > 0 && g->vx > 0 && g->vy > 0 && g->vz > 0))
-    return fail(DC_EINVAL, "pitches and voxel sizes must be positive");
-  const double hx = 0.5 * g->nx * g->vx, hy = 0.5 * g->ny * g->vy, hz = 0.5 * g->nz * g->vz;
-  for (int v = 0; v < n; ++v) {
-    const dc_view& w = views[v];
-    double nx_ = std::sqrt(dot3(w.ex, w.ex)), ny_ = std::sqrt(dot3(w.ey, w.ey));
-    if (std::fabs(nx_ - 1) > 1e-9 || std::fabs(ny_ - 1) > 1e-9 || std::fabs(dot3(w.ex, w.ey)) > 1e-9)
-      return fail(DC_EINVAL, "view " + std::to_string(v) + ": detector axes not orthonormal");
-    double lz[3], d[3];
-    cross3(w.ex, w.ey, lz);
-    for (int c = 0; c < 3; ++c) d[c] = w.src[c] - w.det_center[c];
-    double D = dot3(d, lz);
-    if (!(D > 0)) return fail(DC_EINVAL, "view " + std::to_string(v) + ": source not in front of the detector");
-    double off = 0;
-    for (int c = 0; c < 3; ++c) off += (d[c] - D * lz[c]) * (d[c] - D * lz[c]);
-    if (std::sqrt(off) > 1e-6 * D)
-      return fail(DC_EINVAL, "view " + std::to_string(v) + ": source not on the detector normal through its centre");
-    for (int corner = 0; corner < 8; ++corner) {
-      double p[3] = {g->ox + ((corner & 1) ? hx : -hx), g->oy + ((corner & 2) ? hy : -hy),
-                     g->oz + ((corner & 4) ? hz : -hz)};
-      double U = 0;
-      for (int c = 0; c < 3; ++c) U += (w.src[c] - p[c]) * lz[c];
-      if (!(U > 1e-6 * D))
-        return fail(DC_EINVAL, "view " + std::to_string(v) + ": volume not entirely in front of the source");
-    }
-  }
-  return DC_OK;
+  std::string err;
+  const dc_status st = validate_geometry(g, views, n, &err);
+  if (st != DC_OK) set_error(err);
+  return st;
 }
 
-
-// Largest number of voxel centres the cone adjoint may add into one accumulator
-// (one detector cell in one view); its fixed-point quantum is 2^30 / this of the
-// largest term, so beyond it the adjoint would lose float32 accuracy.
-static const int kMaxCellTerms = 1 << 18;
-
-// Upper bound on the voxel centres whose projection in view w falls in one
-// detector cell [i, i+1) x [j, j+1) of fractional indices.  Points of the cell's
-// frustum are x = a + U (alpha l_x + beta l_y - l_z), U the depth, the cell
-// spanning du/D in alpha and dv/D in beta.  Slice the centre lattice along an
-// axis k over which x_k - a_k keeps one sign on the box.  Two frustum points x1,
-// x2 in one slice differ by U1 (delta - (delta_k / d2_k) d2), d2 = (x2 - a)/U2,
-// delta = d1 - d2 = dalpha l_x + dbeta l_y; along an in-slice axis b that is at
-// most  U_max (du/D |l_x,b - t l_x,k| + dv/D |l_y,b - t l_y,k|),
-// t = (x2_b - a_b)/(x2_k - a_k), whose extremes over the box (a linear-fractional
-// function with a denominator of fixed sign) sit at its corners.  A slice thus
-// holds at most (floor(E_b/v_b)+1)(floor(E_c/v_c)+1) centres and the box has
-// n_k slices; the smallest such product over the admissible axes is the bound.
-static double cell_terms_bound(const dc_grid* g, const dc_view& w, double D,
-                               const double X0[3], double umax) {
-  const int n[3] = {g->nx, g->ny, g->nz};
-  const double vs[3] = {g->vx, g->vy, g->vz};
-  double corner[8][3];
-  for (int c = 0; c < 8; ++c)
-    for (int k = 0; k < 3; ++k) corner[c][k] = X0[k] + ((c >> k) & 1) * (n[k] - 1) * vs[k] - w.src[k];
-  double best = 1e300;
-  for (int k = 0; k < 3; ++k) {
-    bool pos = true, neg = true;
-    for (int c = 0; c < 8; ++c) {
-      pos = pos && corner[c][k] > 0.0;
-      neg = neg && corner[c][k] < 0.0;
-    }
-    if (!pos && !neg) continue;   // the source lies within the box's extent along k
-    double count = n[k];
-    for (int b = 0; b < 3; ++b) {
-      if (b == k) continue;
-      double tmin = 1e300, tmax = -1e300;
-      for (int c = 0; c < 8; ++c) {
-        const double t = corner[c][b] / corner[c][k];
-        tmin = std::min(tmin, t);
-        tmax = std::max(tmax, t);
-      }
-      const double sx = std::max(std::fabs(w.ex[b] - tmin * w.ex[k]), std::fabs(w.ex[b] - tmax * w.ex[k]));
-      const double sy = std::max(std::fabs(w.ey[b] - tmin * w.ey[k]), std::fabs(w.ey[b] - tmax * w.ey[k]));
-      const double E = umax * (g->du / D * sx + g->dv / D * sy);
-      count *= std::floor(E / vs[b] * (1.0 + 1e-9)) + 1.0;
-    }
-    best = std::min(best, count);
-  }
-  return best;
+KernelShape kernel_shape() {
+  KernelShape ks;
+  ks.interp_tx = interp_tile(0);
+  ks.interp_ty = interp_tile(1);
+  ks.bp_bx = cone_bp_block(0);
+  ks.bp_by = cone_bp_block(1);
+  ks.bp_bz = cone_bp_block(2);
+  return ks;
 }
 
 static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, const int32_t* first,
@@ -131,181 +49,34 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
   k.du = (float)g->du; k.dv = (float)g->dv; k.ds = (float)g->ds;
   k.cu = 0.5f * (g->nu - 1); k.cv = 0.5f * (g->nv - 1);
 
-  const int K = g->n_theta;
-  std::vector<double> ang(3 * K);
-  std::vector<float> trig(2 * K);
-  const double x0 = -0.5 * (g->nu - 1) * g->du, y0 = -0.5 * (g->nv - 1) * g->dv;
-  int wl = 0;
-  for (int kk = 0; kk < K; ++kk) {
-    double mu = kk * M_PI / K, c = std::cos(mu), s = std::sin(mu);
-    double A = g->du * c / g->ds, B = g->dv * s / g->ds;
-    double C = (x0 * c + y0 * s) / g->ds + 0.5 * (g->n_s - 1);
-    ang[3 * kk] = A; ang[3 * kk + 1] = B; ang[3 * kk + 2] = C;
-    trig[2 * kk] = (float)c; trig[2 * kk + 1] = (float)s;
-    int w = (int)std::ceil((interp_tile(0) - 1) * std::fabs(A) + (interp_tile(1) - 1) * std::fabs(B)) + 4;
-    if (w > wl) wl = w;
-  }
-  p->interp_wl = wl;
-  // the window rows of a chunk of 32 angles take 32 wl 8 bytes of LDS (<= 128 KiB)
-  if (wl > 512) return fail(DC_ENOTSUP, "detector pitch too coarse for the s-bin width (ds << du)");
+  HostPlan hp;
+  std::string err;
+  const dc_status st = plan_tables(g, views, n, first, n_samples, kernel_shape(), &hp, &err);
+  if (st != DC_OK) return fail(st, err);
+  p->interp_wl = hp.interp_wl;
+  p->splat_kc = hp.splat_kc;
+  p->splat_max_terms = hp.splat_max_terms;
+  p->splat_checked = hp.splat_checked;
+  p->n_chunks = hp.n_chunks;
+  p->cone_max_terms = hp.cone_max_terms;
+  p->bp_stage = hp.bp_stage;
+  p->cone_form = hp.cone_form;
+  p->splat_qmax = fixed_point_qmax(hp.splat_max_terms);
+  p->cone_qmax = fixed_point_qmax(hp.cone_max_terms);
 
-  // Radon work list: runs of angles whose pixels spread fastest along rows
-  // (|A| >= |B|, lanes walk i) or along columns (lanes walk j), cut into chunks.
-  // LDS holds kc rows of (n_s + 1) 64-bit accumulators, at most 80 KiB so that two
-  // workgroups share a CU's 160 KiB (1381 bins, a 976^2 detector: 7 angles, 15-17% faster than
-  // the 5 a 64 KiB budget allows)
-  const int kc = std::max(1, std::min(8, 10240 / (g->n_s + 1)));
-  p->splat_kc = kc;
-  // bound on pixels sharing one bin on one angle, and whether every pixel's
-  // bin index stays in [-1, n_s - 1] (then the splat needs no range checks)
-  {
-    int max_terms = 1;
-    bool inside = true;
-    for (int kk = 0; kk < K; ++kk) {
-      const double A = std::fabs(ang[3 * kk]), B = std::fabs(ang[3 * kk + 1]);
-      const double per_row = A > 0 ? std::floor(1.0 / A) + 1 : 1e30;
-      const double per_col = B > 0 ? std::floor(1.0 / B) + 1 : 1e30;
-      const double terms = std::min(per_row * g->nv, per_col * g->nu);
-      max_terms = std::max(max_terms, (int)std::min(terms, (double)g->nu * g->nv));
-      for (int c = 0; c < 4; ++c) {
-        const double t = ang[3 * kk + 2] + ((c & 1) ? (g->nu - 1) * ang[3 * kk] : 0.0) +
-                         ((c & 2) ? (g->nv - 1) * ang[3 * kk + 1] : 0.0);
-        if (!(t >= -0.999 && t < g->n_s - 0.001)) inside = false;
-      }
-    }
-    p->splat_max_terms = max_terms;
-    p->splat_checked = inside ? 0 : 1;
-  }
-  std::vector<int> chunks;
-  for (int kk = 0; kk < K;) {
-    int colmajor = std::fabs(ang[3 * kk + 1]) > std::fabs(ang[3 * kk]) ? 1 : 0;
-    int e = kk;
-    while (e < K && e - kk < kc &&
-           (std::fabs(ang[3 * e + 1]) > std::fabs(ang[3 * e]) ? 1 : 0) == colmajor) ++e;
-    chunks.insert(chunks.end(), {kk, e - kk, colmajor, 0});
-    kk = e;
-  }
-  p->n_chunks = (int)chunks.size() / 4;
-
-  std::vector<float> vf(4 * n), rmax2(n);
-  std::vector<double> frame(12 * n);
-  for (int v = 0; v < n; ++v)
-    for (int c = 0; c < 3; ++c) {
-      frame[12 * v + c] = views[v].src[c];
-      frame[12 * v + 3 + c] = views[v].det_center[c];
-      frame[12 * v + 6 + c] = views[v].ex[c];
-      frame[12 * v + 9 + c] = views[v].ey[c];
-    }
-  std::vector<double> proj(12 * n), zrel(n);
-  double max_cell_terms = 0.0;
-  const double X0[3] = {-0.5 * (g->nx - 1) * g->vx + g->ox, -0.5 * (g->ny - 1) * g->vy + g->oy,
-                        -0.5 * (g->nz - 1) * g->vz + g->oz};
-  const double vs[3] = {g->vx, g->vy, g->vz};
-  const double four_pi2 = 4.0 * M_PI * M_PI;
-  for (int v = 0; v < n; ++v) {
-    const dc_view& w = views[v];
-    double lz[3], d[3];
-    cross3(w.ex, w.ey, lz);
-    for (int c = 0; c < 3; ++c) d[c] = w.src[c] - w.det_center[c];
-    double D = dot3(d, lz);
-    vf[4 * v] = (float)D;
-    vf[4 * v + 1] = (float)(dot3(w.tangent, w.ex) / (four_pi2 * D));
-    vf[4 * v + 2] = (float)(dot3(w.tangent, w.ey) / (four_pi2 * D));
-    vf[4 * v + 3] = (float)(dot3(w.tangent, lz) / (four_pi2 * D * D));
-    double rel0[3];
-    for (int c = 0; c < 3; ++c) rel0[c] = X0[c] - w.src[c];
-    double* P = &proj[12 * v];
-    for (int c = 0; c < 3; ++c) {
-      double dn = -vs[c] * lz[c] / D;
-      P[c] = dn;
-      P[4 + c] = vs[c] * w.ex[c] / g->du + 0.5 * (g->nu - 1) * dn;
-      P[8 + c] = vs[c] * w.ey[c] / g->dv + 0.5 * (g->nv - 1) * dn;
-    }
-    double dn0 = -dot3(rel0, lz) / D;
-    P[3] = dn0;
-    // depth range over the box of voxel centres (affine, extremes at corners)
-    double umin = 1e300, umax = 0.0;
-    for (int corner = 0; corner < 8; ++corner) {
-      double den = dn0;
-      for (int c = 0; c < 3; ++c) {
-        const int nn = c == 0 ? g->nx : c == 1 ? g->ny : g->nz;
-        if (corner & (1 << c)) den += P[c] * (nn - 1);
-      }
-      umin = std::min(umin, den * D);
-      umax = std::max(umax, den * D);
-    }
-    rmax2[v] = (float)((D / umin) * (D / umin) * (1.0 + 1e-6));
-    zrel[v] = std::fabs(P[2]) / (umin / D);   // largest relative change of den per voxel step in z
-    max_cell_terms = std::max(max_cell_terms, cell_terms_bound(g, w, D, X0, umax));
-    P[7] = dot3(rel0, w.ex) / g->du + 0.5 * (g->nu - 1) * dn0;
-    P[11] = dot3(rel0, w.ey) / g->dv + 0.5 * (g->nv - 1) * dn0;
-  }
-
-  if (max_cell_terms > (double)kMaxCellTerms)
-    return fail(DC_ENOTSUP, "up to " + std::to_string((long long)max_cell_terms) +
-                                " voxel centres can project into one detector cell (limit " +
-                                std::to_string(kMaxCellTerms) + "); the detector is too coarse for the voxel grid");
-  p->cone_max_terms = (int)std::max(1.0, max_cell_terms);
-  // largest backprojection block footprint (same box rule as the kernel) ->
-  // how many pixels each of the backprojection's threads stages per view
-  {
-    const int B[3] = {cone_bp_block(0), cone_bp_block(1), cone_bp_block(2)};
-    const int nb[3] = {(g->nx + B[0] - 1) / B[0], (g->ny + B[1] - 1) / B[1], (g->nz + B[2] - 1) / B[2]};
-    double worst = 0;
-    for (int v = 0; v < n; ++v) {
-      const double* P = &proj[12 * v];
-      for (int bz = 0; bz < nb[2]; ++bz)
-        for (int by = 0; by < nb[1]; ++by)
-          for (int bx = 0; bx < nb[0]; ++bx) {
-            const int lo[3] = {bx * B[0], by * B[1], bz * B[2]};
-            const int hi[3] = {std::min(g->nx, lo[0] + B[0]) - 1, std::min(g->ny, lo[1] + B[1]) - 1,
-                               std::min(g->nz, lo[2] + B[2]) - 1};
-            double imin = 1e300, imax = -1e300, jmin = 1e300, jmax = -1e300;
-            for (int c = 0; c < 8; ++c) {
-              const double x = (c & 1) ? hi[0] : lo[0], y = (c & 2) ? hi[1] : lo[1], z = (c & 4) ? hi[2] : lo[2];
-              const double den = x * P[0] + y * P[1] + z * P[2] + P[3];
-              const double iu = (x * P[4] + y * P[5] + z * P[6] + P[7]) / den;
-              const double jv = (x * P[8] + y * P[9] + z * P[10] + P[11]) / den;
-              imin = std::min(imin, iu); imax = std::max(imax, iu);
-              jmin = std::min(jmin, jv); jmax = std::max(jmax, jv);
-            }
-            // kernel box: [floor(min)-1, floor(max)+2], plus slack for float rounding
-            const double w = std::floor(imax) - std::floor(imin) + 5, h = std::floor(jmax) - std::floor(jmin) + 5;
-            worst = std::max(worst, w * h);
-          }
-    }
-    const int need = (int)std::ceil(worst / (double)cone_bp_threads());
-    p->bp_stage = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 0;
-    // Form of the cone kernels, decided per sample (so a batched plan computes what
-    // each scan's own plan does).  den = U/D and num_u free of z on every view: a
-    // voxel column keeps one u and one weight per view, formed once per column.
-    // Otherwise, if den changes by at most 2.5e-4 of itself per voxel step, one
-    // Newton step from the previous voxel's reciprocal leaves a relative error of
-    // that change squared (< 6.3e-8, float rounding) and replaces the reciprocal.
-    p->cone_form.assign(p->first.size() - 1, kConeZinv);
-    for (size_t smp = 0; smp + 1 < p->first.size(); ++smp) {
-      bool zinv = true;
-      double worst = 0.0;
-      for (int v = p->first[smp]; v < p->first[smp + 1]; ++v) {
-        zinv = zinv && proj[12 * v + 2] == 0.0 && proj[12 * v + 6] == 0.0;
-        worst = std::max(worst, zrel[v]);
-      }
-      p->cone_form[smp] = zinv ? kConeZinv : worst <= 2.5e-4 ? kConeNewton : kConeGeneral;
-    }
-  }
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dst, bytes);
     if (e != hipSuccess) return e;
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   hipError_t e;
-  if ((e = up((void**)&p->d_ang, ang.data(), ang.size() * sizeof(double))) != hipSuccess ||
-      (e = up((void**)&p->d_trig, trig.data(), trig.size() * sizeof(float))) != hipSuccess ||
-      (e = up((void**)&p->d_view, vf.data(), vf.size() * sizeof(float))) != hipSuccess ||
-      (e = up((void**)&p->d_frame, frame.data(), frame.size() * sizeof(double))) != hipSuccess ||
-      (e = up((void**)&p->d_proj, proj.data(), proj.size() * sizeof(double))) != hipSuccess ||
-      (e = up((void**)&p->d_rmax2, rmax2.data(), rmax2.size() * sizeof(float))) != hipSuccess ||
-      (e = up((void**)&p->d_chunks, chunks.data(), chunks.size() * sizeof(int))) != hipSuccess ||
+  if ((e = up((void**)&p->d_ang, hp.ang.data(), hp.ang.size() * sizeof(double))) != hipSuccess ||
+      (e = up((void**)&p->d_trig, hp.trig.data(), hp.trig.size() * sizeof(float))) != hipSuccess ||
+      (e = up((void**)&p->d_view, hp.vf.data(), hp.vf.size() * sizeof(float))) != hipSuccess ||
+      (e = up((void**)&p->d_frame, hp.frame.data(), hp.frame.size() * sizeof(double))) != hipSuccess ||
+      (e = up((void**)&p->d_proj, hp.proj.data(), hp.proj.size() * sizeof(double))) != hipSuccess ||
+      (e = up((void**)&p->d_rmax2, hp.rmax2.data(), hp.rmax2.size() * sizeof(float))) != hipSuccess ||
+      (e = up((void**)&p->d_chunks, hp.chunks.data(), hp.chunks.size() * sizeof(int))) != hipSuccess ||
       (e = up((void**)&p->d_first, p->first.data(), p->first.size() * sizeof(int))) != hipSuccess ||
       (e = hipMalloc((void**)&p->d_scratch, (n + n_samples) * sizeof(unsigned))) != hipSuccess ||
       (e = hipMalloc((void**)&p->d_masked, (size_t)n_samples * g->nx * g->ny * g->nz * sizeof(float))) !=
@@ -423,6 +194,34 @@ dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_vi
 dc_status dc_plan_create_batched(const dc_grid* grid, const dc_view* views, int32_t n_views,
                                  const int32_t* first_view, int32_t n_samples, uint32_t flags, dc_plan* out) {
   return create(grid, views, n_views, first_view, n_samples, flags, out);
+}
+
+dc_status dc_plan_bounds(const dc_grid* grid, const dc_view* views, int32_t n_views, dc_bounds* out) {
+  if (!out) return fail(DC_EINVAL, "null output bounds pointer");
+  DC_TRY(validate(grid, views, n_views));
+  HostPlan hp;
+  std::string err;
+  const int32_t first[2] = {0, n_views};
+  const dc_status st = plan_tables(grid, views, n_views, first, 1, kernel_shape(), &hp, &err);
+  if (st != DC_OK) return fail(st, err);
+  dc_bounds b{};
+  b.splat_angles = hp.splat_kc;
+  b.splat_max_terms = hp.splat_max_terms;
+  b.splat_checked = hp.splat_checked;
+  b.interp_window = hp.interp_wl;
+  b.interp_local = hp.interp_wl > kInterpLocalAbove ? 1 : 0;
+  b.cone_max_terms = hp.cone_max_terms;
+  b.bp_stage = hp.bp_stage;
+  b.cone_form = hp.cone_form[0];
+  b.splat_qmax = fixed_point_qmax(hp.splat_max_terms);
+  b.cone_qmax = fixed_point_qmax(hp.cone_max_terms);
+  b.bp_block[0] = cone_bp_block(0);
+  b.bp_block[1] = cone_bp_block(1);
+  b.bp_block[2] = cone_bp_block(2);
+  b.interp_tile[0] = interp_tile(0);
+  b.interp_tile[1] = interp_tile(1);
+  *out = b;
+  return DC_OK;
 }
 
 dc_status dc_plan_destroy(dc_plan plan) {

@@ -426,7 +426,7 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
 template <typename Tout, bool CLAMP, int FORM>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
                                                  const double* __restrict__ proj, const float* __restrict__ rmax2,
-                                                 int v0, int nv, int tiles_u, int n_tiles, int max_terms,
+                                                 int v0, int nv, int tiles_u, int n_tiles, float qmax,
                                                  const unsigned* __restrict__ gmax_bits,
                                                  const int* __restrict__ first, int s_lo, int s_hi, int ngroups) {
   __shared__ double sL[kFV][4][4], sNegInvA[kFV][4];
@@ -513,7 +513,6 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   __syncthreads();
   const int nrows = sNL * g.ny;
   const int plane = g.nx * g.ny;   // volumes are below 2^31 voxels (checked by the plan)
-  const float qmax = fminf(floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f), 2097152.0f);
   const float gabs = __uint_as_float(gmax_bits[smp]);
   float S[kFV];
 #pragma unroll
@@ -799,7 +798,7 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
         const dim3 grid(8 * ((n_tiles + 7) / 8) * ng);
 #define DC_FP(C, Z)                                                                                              \
   hipLaunchKernelGGL((k_cone_fp<T, C, Z>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, nv, \
-                     tiles_u, n_tiles, p.cone_max_terms, gmax, p.d_first, a, b, ng)
+                     tiles_u, n_tiles, p.cone_qmax, gmax, p.d_first, a, b, ng)
         const bool clamp = top >= 4294967296.0;
         switch (p.cone_form[a]) {
           case kConeZinv: if (clamp) DC_FP(true, kConeZinv); else DC_FP(false, kConeZinv); break;

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "dcfbp.h"
+#include "plan_host.h"
 
 namespace dc {
 
@@ -48,7 +49,6 @@ struct KGrid {
 };
 
 // Plan: host copy of the geometry plus small device tables.
-enum ConeForm : char { kConeGeneral = 0, kConeNewton = 1, kConeZinv = 2 };
 
 struct Plan {
   int device = 0;
@@ -94,7 +94,13 @@ struct Plan {
   int splat_checked = 1;         // 0 when every pixel lands on bins [-1, n_s) for all angles
   int interp_wl = 0;             // LDS window length for the interpolating kernels
                                  // (above kInterpLocalAbove: the midpoint-local tap form)
+  // fixed-point scales: a sum of the splat (cone FP) holds terms of at most qmax
+  // units, qmax = fixed_point_qmax(splat_max_terms (cone_max_terms))
+  float splat_qmax = 0.f, cone_qmax = 0.f;
 };
+
+// Kernel shapes the plan's bounds are derived for (api.hip).
+KernelShape kernel_shape();
 
 void set_error(const std::string& msg);
 

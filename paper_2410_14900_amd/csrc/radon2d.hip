@@ -25,8 +25,8 @@ namespace dc {
 // ones run at full LDS rate).  Integer addition is associative, so the result is
 // bit-reproducible.  The fixed-point scale is per view: a small reduction kernel
 // writes max|x| over each view to the plan's scratch, and the quantum is sized so
-// that no bin's a-sum can leave 32 bits (at most `max_terms` pixels share a bin
-// on one angle).
+// that no bin's a-sum can leave 32 bits (the plan bounds how many pixels share
+// a bin on one angle).
 //
 // The fractional bin t reaches ~n_s, where a float32 ulp is 1e-4 bin; it is kept
 // in exact 32.32 fixed point instead (see the walk below).
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
                                                const int4* __restrict__ chunks,
                                                const double* __restrict__ angd,
                                                const float4* __restrict__ viewf, float scale, int v0, int nv,
-                                               int n_chunks, int max_terms, const unsigned* __restrict__ vmax_bits) {
+                                               int n_chunks, float qmax, const unsigned* __restrict__ vmax_bits) {
   extern __shared__ unsigned long long acc[];   // [kn][n_s + 1], index m + 1
   __shared__ double sA[16], sB[16], sC[16];
   __shared__ long long sStep[16];
@@ -106,9 +106,9 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
   }
   __syncthreads();
   const float vmax = __uint_as_float(vmax_bits[v]);
-  // quantum: |a| per bin stays below 2^31 - 1 with max_terms contributions, and
-  // every term below 2^21 so the rounding below is exact
-  const float qmax = fminf(floorf(2147483647.0f / (float)(max_terms + 1) * 0.5f), 2097152.0f);
+  // quantum: the largest term takes qmax units (fixed_point_qmax of the plan's
+  // bound on pixels per bin), so |a| per bin stays in 31 bits and every term
+  // below 2^21, where the rounding below is exact
   const float S = vmax > 0.f ? qmax / vmax : 0.f;
   // Threads own whole lines of pixels (columns when the angles spread rows,
   // rows otherwise) and walk them; t advances by an exact fixed-point step, so
@@ -222,11 +222,14 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
 // derived from float64 per-(tile, angle) offsets, which keeps them below ~95
 // bins and their float32 rounding below 6e-6 bins.
 // LOCAL: windows wider than kInterpLocalAbove intervals (bins much finer than
-// pixels) store (midpoint, slope) per interval instead and evaluate each tap as
-// mid + (th - round(th)) slope, whose rounding does not grow with the distance
-// from the window centre (two more VALU per tap).  In the (c, s) form the error
-// grows with |th| <= wl/2: a float32 emulation against a float64 lerp gives
-// 3.3e-6 at wl = 94, 9.1e-6 at 254 and 1.8e-5 at 503.
+// pixels) keep each pixel's position t - w0 in exact 32.32 fixed point, set up
+// in float64 per (pixel, angle) and advanced by an exact step over the thread's
+// 8 rows, and store (left sample, slope) per interval: a tap is the interval
+// index (high word), its fraction (low word, 23 bits as a float in [0, 1)) and
+// one FMA.  In the float form the position is a float32 of magnitude up to
+// wl/2 whose rounding (and that of A, B in float32) grows with the window: at
+// bins a fifth of the pixel pitch (wl = 450) it leaves 1.2e-5 against the
+// oracle, above the float32 bar.
 static constexpr int kTX = 64, kTY = 64, kKC = 32;
 static constexpr int kIPThreads = kTX * 8;   // 512: 8 row groups
 static constexpr int kTPX = kTY / 8;   // pixels per thread (rows 8 apart)
@@ -241,6 +244,8 @@ __global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ r
   extern __shared__ float2 win[];
   __shared__ float4 sPar[kKC];   // A, B, t(tile origin) - w0 - 0.5 - wc, kk * wl + wc - bits(1.5 2^23) (int bits)
   __shared__ int sW0[kKC];       // first bin of each angle's window
+  __shared__ double sParD[LOCAL ? kKC : 1][3];     // LOCAL: A, B, t(tile origin) - w0 in float64
+  __shared__ long long sStep8[LOCAL ? kKC : 1];    // LOCAL: 8 B in 32.32 fixed point
   // XCD-aware order: all tiles of a view run on one XCD (its sinogram stays in one L2)
   const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
   const int vl = xcd + 8 * (kb / n_tiles);
@@ -267,6 +272,12 @@ __global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ r
       sW0[threadIdx.x] = w0;
       sPar[threadIdx.x] = make_float4((float)A, (float)B, (float)(t00 - w0 - 0.5 - (wl >> 1)),
                                       __int_as_float((int)((unsigned)(threadIdx.x * wl + (wl >> 1)) - kRoundMagicBits)));
+      if (LOCAL) {
+        sParD[threadIdx.x][0] = A;
+        sParD[threadIdx.x][1] = B;
+        sParD[threadIdx.x][2] = t00 - w0;
+        sStep8[threadIdx.x] = (long long)llrint(8.0 * B * 4294967296.0);
+      }
     }
     __syncthreads();
     for (int q = threadIdx.x; q < kn * wl; q += blockDim.x) {
@@ -275,13 +286,32 @@ __global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ r
       const Tin* r = rv + (size_t)(k0 + kk) * ns;
       const float a = ((unsigned)m < (unsigned)ns) ? to_f32(r[m]) : 0.f;
       const float b = ((unsigned)(m + 1) < (unsigned)ns) ? to_f32(r[m + 1]) : 0.f;
-      // midpoint (a + b) / 2 at th = e - wc, slope b - a; the (c, s) form moves the
-      // midpoint to the window centre
-      win[q] = LOCAL ? make_float2(0.5f * (a + b), b - a)
+      // float form: midpoint (a + b) / 2 at th = e - wc, slope b - a, moved to the
+      // window centre; LOCAL: left sample and slope
+      win[q] = LOCAL ? make_float2(a, b - a)
                      : make_float2(0.5f * (a + b) - (float)(e - (wl >> 1)) * (b - a), b - a);
     }
     __syncthreads();
     const float fx = (float)tx, fy = (float)ty;
+    if constexpr (LOCAL) {
+      for (int kk = 0; kk < kn; ++kk) {
+        // t - w0 >= 1 for every pixel of the tile (w0 is one below the tile's lowest bin)
+        const double ud = fma((double)tx, sParD[kk][0], fma((double)ty, sParD[kk][1], sParD[kk][2]));
+        const double fl = floor(ud);
+        long long u = ((long long)((int)fl + kk * wl) << 32) | (long long)(unsigned)((ud - fl) * 4294967296.0);
+        const long long step = sStep8[kk];
+#pragma unroll
+        for (int h = 0; h < kTPX; ++h) {
+          const unsigned lo = (unsigned)u;
+          const float fr = __uint_as_float((lo >> 9) | 0x3f800000u) - 1.0f;   // fraction, 23 bits
+          const float2 pr = win[(int)(u >> 32)];
+          acc[h] += fmaf(fr, pr.y, pr.x);
+          u += step;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     for (int kk = 0; kk < kn; ++kk) {
       const float4 P = sPar[kk];
       // th = t - 0.5 relative to the window centre; rounding it to the nearest
@@ -295,8 +325,7 @@ __global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ r
         const float th = fmaf((float)h, b8, th0);
         const float y = th + kRoundMagic;
         const float2 pr = win[__float_as_uint(y) + nbias];
-        if (LOCAL) acc[h] += fmaf(th - (y - kRoundMagic), pr.y, pr.x);   // offset from the midpoint, |.| <= 1/2
-        else acc[h] += fmaf(th, pr.y, pr.x);
+        acc[h] += fmaf(th, pr.y, pr.x);
       }
     }
     __syncthreads();
@@ -341,7 +370,7 @@ hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos
       using Tout = decltype(tout);
 #define DC_SPLAT(W, C)                                                                                         \
   hipLaunchKernelGGL((k_splat<Tin, Tout, W, C>), grid, dim3(512), lds, s, (const Tin*)img, (Tout*)out, p.kg,  \
-                     p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, nv, p.n_chunks, p.splat_max_terms, \
+                     p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, nv, p.n_chunks, p.splat_qmax, \
                      p.d_scratch)
       if (wcos) {
         if (p.splat_checked) DC_SPLAT(true, true); else DC_SPLAT(true, false);

@@ -39,6 +39,18 @@ def validate(grid, views):
     return st, (_lib.last_error() if st else "")
 
 
+def plan_bounds(grid, views):
+    """Host-only bounds and kernel forms of a one-scan plan (dc_plan_bounds), as a dict."""
+    g = make_grid(grid)
+    buf, n = make_views(views)
+    b = _lib.DcBounds()
+    check(_lib.lib().dc_plan_bounds(ctypes.byref(g), buf, n, ctypes.byref(b)), "dc_plan_bounds")
+    out = {name: getattr(b, name) for name, _ in _lib.DcBounds._fields_}
+    out["bp_block"] = tuple(b.bp_block)
+    out["interp_tile"] = tuple(b.interp_tile)
+    return out
+
+
 class Plan:
     """Geometry plan on the current device (small float64-derived tables).
 

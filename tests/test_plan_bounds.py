@@ -1,0 +1,291 @@
+"""The plan's safety bounds on the CPU (no GPU): brute-force counts against the
+host-only query dc_plan_bounds, and the host plan code under ASan/UBSan.
+
+The fixed-point stages rely on three bounds the plan derives in float64:
+  * splat_max_terms: pixels whose bin floor(t) is one given bin on one angle
+    (a 32-bit half of the splat's accumulator holds that many terms);
+  * cone_max_terms: voxel centres projecting into one detector cell of one view
+    (the same for the cone FP's accumulators);
+  * bp_stage: the cone BP stages each voxel block's detector footprint in LDS,
+    so the footprint of every block must fit the staged pixels;
+plus the detector BP's window, which must hold every bin interval a pixel tile
+touches on one angle.  Each is compared here with counts over every pixel,
+voxel, block and tile of the geometry.
+"""
+import json
+import math
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pipeline as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2410_14900_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2410_14900_amd as P
+    return P
+
+
+def deep_volume():
+    return (synth.Grid(nu=256, nv=256, du=2.0, dv=2.0, n_theta=20, n_s=synth.radon_bins(256, 256), ds=2.0,
+                       nx=12, ny=12, nz=1024, vx=1.0, vy=1.0, vz=0.3),
+            synth.sinusoid_orbit(5, 750.0, 1200.0))
+
+
+def shallow_volume():
+    return (synth.Grid(nu=704, nv=128, du=1.0, dv=4.0, n_theta=8, n_s=synth.radon_bins(704, 128), ds=1.0,
+                       nx=8200, ny=8192, nz=1, vx=0.05, vy=0.05, vz=0.5, oz=100.0),
+            synth.circle_orbit(3, 750.0, 1200.0).subset([1]))
+
+
+def c2_subset():
+    g, v = synth.config_geometry("C2")
+    return g, v.subset([0, 248])
+
+
+def c3_subset():
+    g, v = synth.config_geometry("C3")
+    return g, v.subset([0, 99, 280])
+
+
+CASES = {
+    "C1": lambda: synth.config_geometry("C1"),
+    "C2-subset": c2_subset,
+    "C3-subset": c3_subset,
+    "deep": deep_volume,
+    "shallow": shallow_volume,
+    "fine-bins": lambda: (synth.Grid(nu=64, nv=48, du=1.0, dv=1.0, n_theta=24, n_s=400, ds=0.2,
+                                     nx=12, ny=12, nz=10, vx=1.0, vy=1.0, vz=1.0),
+                          synth.sinusoid_orbit(3, 750.0, 1200.0)),
+    "narrow-sinogram": lambda: (synth.Grid(nu=70, nv=53, du=1.0, dv=1.0, n_theta=30, n_s=41, ds=1.0,
+                                           nx=20, ny=20, nz=16, vx=1.0, vy=1.0, vz=1.0),
+                                synth.sinusoid_orbit(3, 750.0, 1200.0)),
+}
+
+
+# ------------------------------------------------------------ brute force
+def pixels_per_bin(g):
+    """Largest number of pixels whose bin floor(t) is one bin on one angle, and
+    whether every pixel's bin lies in [-1, n_s - 1]."""
+    worst, inside = 0, True
+    for k in range(g.n_theta):
+        m = np.floor(O._bin_position(g, k)).astype(np.int64).ravel()
+        inside = inside and m.min() >= -1 and m.max() <= g.n_s - 1
+        worst = max(worst, int(np.bincount(m - m.min()).max()))
+    return worst, inside
+
+
+def _voxel_chunks(g, points=1 << 21):
+    """Voxel indices (iz, iy, ix) in chunks of about `points` voxels (whole slices,
+    or blocks of rows of one slice)."""
+    plane = g.nx * g.ny
+    if plane <= points:
+        zc = max(1, points // plane)
+        for z0 in range(0, g.nz, zc):
+            zz, yy, xx = np.meshgrid(np.arange(z0, min(g.nz, z0 + zc)), np.arange(g.ny), np.arange(g.nx),
+                                     indexing="ij")
+            yield np.stack([zz.ravel(), yy.ravel(), xx.ravel()], axis=1)
+    else:
+        rows = max(1, points // g.nx)
+        for iz in range(g.nz):
+            for y0 in range(0, g.ny, rows):
+                yy, xx = np.meshgrid(np.arange(y0, min(g.ny, y0 + rows)), np.arange(g.nx), indexing="ij")
+                yield np.stack([np.full(yy.size, iz), yy.ravel(), xx.ravel()], axis=1)
+
+
+def voxels_per_cell(g, views):
+    """Largest number of voxel centres whose projection floor(i*), floor(j*) is one
+    detector cell, over the views."""
+    worst = 0
+    for v in range(len(views)):
+        one = views.subset([v])
+        counts = None
+        lo = None
+        for idx in _voxel_chunks(g):
+            i_s, j_s, _, _ = O.project_points(O.voxel_centres(g, idx), g, one, 0)
+            ii, jj = np.floor(i_s).astype(np.int64), np.floor(j_s).astype(np.int64)
+            if counts is None:
+                # the volume's image lies within the detector plus a few hundred cells here
+                lo = (int(ii.min()) - 4 * g.nu - 8, int(jj.min()) - 4 * g.nv - 8)
+                W, H = 9 * g.nu + 16, 9 * g.nv + 16
+                counts = np.zeros(W * H, np.int64)
+            key = (jj - lo[1]) * W + (ii - lo[0])
+            assert key.min() >= 0 and key.max() < W * H
+            counts += np.bincount(key, minlength=W * H)
+        worst = max(worst, int(counts.max()))
+    return worst
+
+
+def block_tap_extent(g, views, block):
+    """Largest (width + 2) x (height + 2) of the detector pixels the bilinear taps of
+    one cone-BP voxel block reach on one view (one pixel of margin each side)."""
+    bx, by, bz = block
+    rows = by * max(1, 2 ** 21 // (by * g.nx * bz))        # about 2M voxels per chunk
+    nxp = -(-g.nx // bx) * bx
+    worst = 0
+    for v in range(len(views)):
+        one = views.subset([v])
+        for z0 in range(0, g.nz, bz):
+            for y0 in range(0, g.ny, rows):
+                z = np.arange(z0, min(g.nz, z0 + bz))
+                y = np.arange(y0, min(g.ny, y0 + rows))
+                zz, yy, xx = np.meshgrid(z, y, np.arange(g.nx), indexing="ij")
+                idx = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], axis=1)
+                i_s, j_s, _, _ = O.project_points(O.voxel_centres(g, idx), g, one, 0)
+                nyp = -(-len(y) // by) * by
+                ext = []
+                for a in (np.floor(i_s), np.floor(j_s)):
+                    a = a.reshape(len(z), len(y), g.nx)
+                    a = np.pad(a, ((0, bz - len(z)), (0, nyp - len(y)), (0, nxp - g.nx)), constant_values=np.nan)
+                    a = a.reshape(bz, nyp // by, by, nxp // bx, bx)
+                    ext.append(np.nanmax(a, axis=(0, 2, 4)) - np.nanmin(a, axis=(0, 2, 4)) + 2)
+                worst = max(worst, int(np.nanmax((ext[0] + 2) * (ext[1] + 2))))
+    return worst
+
+
+def tile_window_need(g, tile):
+    """Largest floor(tmax) - floor(tmin) + 2 over the pixel tiles of the detector BP
+    (whole tiles, as the kernel evaluates them) and the angles: the bin intervals
+    one angle's window must hold, one below the first included."""
+    tx, ty = tile
+    worst = 0
+    for k in range(g.n_theta):
+        mu = k * math.pi / g.n_theta
+        A, B = g.du * math.cos(mu) / g.ds, g.dv * math.sin(mu) / g.ds
+        for j0 in range(0, g.nv, ty):
+            for i0 in range(0, g.nu, tx):
+                i = np.array([i0, i0 + tx - 1], np.float64)
+                j = np.array([j0, j0 + ty - 1], np.float64)
+                x = (i - (g.nu - 1) / 2.0) * g.du
+                y = (j - (g.nv - 1) / 2.0) * g.dv
+                t = (x[None, :] * math.cos(mu) + y[:, None] * math.sin(mu)) / g.ds + (g.n_s - 1) / 2.0
+                worst = max(worst, int(math.floor(t.max()) - math.floor(t.min())) + 2)
+    return worst
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_plan_bounds_hold_against_brute_force_counts(P, name):
+    g, views = CASES[name]()
+    b = P.plan_bounds(g, views)
+    n_pix, inside = pixels_per_bin(g)
+    assert b["splat_max_terms"] >= n_pix, (b["splat_max_terms"], n_pix)
+    assert b["splat_max_terms"] <= 2 * n_pix + g.nv        # not loose by more than the per-line slack
+    if not inside:
+        assert b["splat_checked"] == 1
+    # a 32-bit accumulator half never overflows: terms of at most qmax + 1/2 units
+    assert n_pix * (b["splat_qmax"] + 0.5) < 2 ** 31
+    n_vox = voxels_per_cell(g, views)
+    assert b["cone_max_terms"] >= n_vox, (b["cone_max_terms"], n_vox)
+    if name != "shallow":   # a grazing slab: the slice bound's bounding box is 22x the count there
+        assert b["cone_max_terms"] <= 2 * n_vox, (b["cone_max_terms"], n_vox)
+    assert n_vox * (b["cone_qmax"] + 0.5) < 2 ** 31
+    assert tile_window_need(g, b["interp_tile"]) <= b["interp_window"] - 1
+    assert b["interp_local"] == (b["interp_window"] > 160)
+    if b["bp_stage"] > 0:
+        threads = b["bp_block"][0] * b["bp_block"][1]
+        assert block_tap_extent(g, views, b["bp_block"]) <= b["bp_stage"] * threads
+    print(name, {k: b[k] for k in ("splat_max_terms", "cone_max_terms", "bp_stage", "interp_window")},
+          "brute:", n_pix, n_vox)
+
+
+def test_cone_bound_is_tight_on_the_circle(P):
+    """On C1's circle the bound on voxel centres per detector cell equals the count
+    (32: a cell's preimage holds one voxel column of the 32-voxel depth)."""
+    g, views = CASES["C1"]()
+    assert P.plan_bounds(g, views)["cone_max_terms"] == 32 == voxels_per_cell(g, views)
+
+
+def test_plan_bounds_reject_what_plans_reject(P):
+    g, views = synth.config_geometry("C1", n_views=4)
+    import dataclasses
+    with pytest.raises(P.DcError, match="DC_ENOTSUP"):       # window of 63 * 10 * sqrt(2) intervals
+        P.plan_bounds(dataclasses.replace(g, ds=0.1, n_s=910), views)
+    with pytest.raises(P.DcError, match="DC_ESHAPE"):
+        P.plan_bounds(dataclasses.replace(g, n_s=4097), views)
+    bad = views.subset([0, 1])
+    bad.ex[1] = [np.nan, 0, 0]
+    with pytest.raises(P.DcError, match="DC_EINVAL"):
+        P.plan_bounds(g, bad)
+
+
+# ------------------------------------------------------------ sanitizers
+def _write_geometry(path, grid, views):
+    from paper_2410_14900_amd import ops
+    gs = ops.make_grid(grid)
+    arr = np.ascontiguousarray(views.packed(), np.float64)
+    with open(path, "wb") as fh:
+        fh.write(struct.pack("<i", arr.shape[0]))
+        fh.write(bytes(gs))
+        fh.write(arr.tobytes())
+
+
+@pytest.fixture(scope="module")
+def sanitized_driver(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    out = str(tmp_path_factory.mktemp("san") / "plan_host_driver")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+           "-I/opt/rocm/include", os.path.join(CSRC, "plan_host.cpp"),
+           os.path.join(ROOT, "tests", "host", "plan_host_driver.cpp"), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return out
+
+
+def _bad_cases():
+    g, views = synth.config_geometry("C1", n_views=4)
+    import dataclasses
+    nan = views.subset([0, 1, 2, 3])
+    nan.ex[2] = [np.nan, 0.0, 0.0]
+    behind = views.subset([0, 1])
+    behind.src[1] = behind.det_center[1] + 0.001 * np.cross(behind.ex[1], behind.ey[1])
+    return {
+        "fine-bins-too-wide": (dataclasses.replace(g, ds=0.1, n_s=910), views),
+        "n_s-too-long": (dataclasses.replace(g, n_s=4097), views),
+        "nan-axis": (g, nan),
+        "source-off-normal": (g, behind),
+        "coarse-detector": (dataclasses.replace(g, du=200.0, dv=200.0, ds=200.0, nx=300, ny=300, nz=300,
+                                                vx=0.01, vy=0.01, vz=0.01), views),
+    }
+
+
+def test_host_plan_code_under_address_and_undefined_sanitizers(P, sanitized_driver, tmp_path):
+    """The host plan code (validation, tables, bounds) built with ASan and UBSan,
+    every error recoverable off: valid and invalid geometries run clean, and
+    the bounds and statuses equal the library's dc_plan_bounds."""
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    cases = {k: f() for k, f in CASES.items() if k != "shallow"}
+    g5, v5 = synth.config_geometry("C5")
+    cases["C5-subset"] = (g5, v5.subset([0, 248]))
+    cases["random-nn"] = (synth.Grid(nu=56, nv=44, du=1.1, dv=1.1, n_theta=41, n_s=synth.radon_bins(56, 44),
+                                     ds=1.1, nx=28, ny=26, nz=24, vx=1.0, vy=1.0, vz=1.0),
+                          synth.random_nn_orbit(9, 750.0, 1200.0, 10.0, 5))
+    cases.update(_bad_cases())
+    for name, (g, views) in cases.items():
+        path = str(tmp_path / (name + ".bin"))
+        _write_geometry(path, g, views)
+        r = subprocess.run([sanitized_driver, path], capture_output=True, text=True, env=env, timeout=300)
+        assert r.returncode == 0 and "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, \
+            (name, r.returncode, r.stderr[-2000:])
+        got = json.loads(r.stdout)
+        try:
+            b = P.plan_bounds(g, views)
+            st = 0
+        except P.DcError as e:
+            st = e.status
+        assert got["status"] == st, (name, got, st)
+        if st == 0:
+            for k in ("splat_angles", "splat_max_terms", "splat_checked", "interp_window", "cone_max_terms",
+                      "bp_stage", "cone_form", "splat_qmax", "cone_qmax"):
+                assert got[k] == b[k], (name, k, got[k], b[k])
