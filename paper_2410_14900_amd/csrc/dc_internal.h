@@ -155,8 +155,10 @@ hipError_t launch_ssim(const float* x, const float* y, int nz, int ny, int nx, f
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 
 // launchers (return hipSuccess or the launch error)
+// vmax_words: nv zeroed-then-reduced words for the per-view fixed-point scales
+// (nullptr: the plan's scratch)
 hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale,
-                        void* out, dc_dtype t_out, int v0, int nv, hipStream_t s);
+                        void* out, dc_dtype t_out, int v0, int nv, hipStream_t s, unsigned* vmax_words = nullptr);
 hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wcos, float scale,
                          void* out, dc_dtype t_out, int v0, int nv, hipStream_t s);
 hipError_t launch_filter(const Plan& p, const void* R, dc_dtype tR, const float* M, int raw,

@@ -7,7 +7,6 @@
 // mu_k, Lambda the hat function and w the optional cosine weight D/sqrt(x^2+y^2+D^2).
 // The two are exact transposes of each other for equal scales.
 #include <algorithm>
-
 #include <type_traits>
 
 #include "dc_internal.h"
@@ -39,7 +38,8 @@ hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// max |w x| over each view, as float bits (non-negative floats order like their bits)
+// max |w x| over each view, as float bits (non-negative floats order like their bits),
+// into vmax[v - v0] (zeroed before)
 template <typename Tin, bool WCOS>
 __global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img, unsigned* __restrict__ vmax, KGrid g,
                                                      const float4* __restrict__ viewf, int v0) {
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img
     if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(vmax + v, __float_as_uint(red[0]));
+  if (threadIdx.x == 0) atomicMax(vmax + blockIdx.y, __float_as_uint(red[0]));   // word of view v0 + y
 }
 
 static constexpr int kSplatKC = 8;   // max angles per workgroup (registers hold one t per angle)
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
     sStep[threadIdx.x] = (long long)llrint((colmajor ? angd[3 * k] : angd[3 * k + 1]) * 4294967296.0);
   }
   __syncthreads();
-  const float vmax = __uint_as_float(vmax_bits[v]);
+  const float vmax = __uint_as_float(vmax_bits[vl]);   // the view's word, indexed from v0
   // quantum: the largest term takes qmax units (fixed_point_qmax of the plan's
   // bound on pixels per bin), so |a| per bin stays in 31 bits and every term
   // below 2^21, where the rounding below is exact
@@ -350,20 +350,22 @@ __global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ r
 // --------------------------------------------------------------- dispatch
 
 hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale, void* out,
-                        dc_dtype t_out, int v0, int nv, hipStream_t s) {
+                        dc_dtype t_out, int v0, int nv, hipStream_t s, unsigned* vmax_words) {
   const size_t lds = (size_t)p.splat_kc * (p.kg.n_s + 1) * sizeof(unsigned long long);
   dim3 grid(8 * ((nv + 7) / 8) * p.n_chunks);
-  hipError_t e = launch_zero_u32(p.d_scratch + v0, nv, s);
+  // one max word per view of the call: the plan's scratch, or the caller's (the static array)
+  unsigned* vmax = vmax_words ? vmax_words : p.d_scratch + v0;
+  hipError_t e = launch_zero_u32(vmax, nv, s);
   if (e != hipSuccess) return e;
   return by_dtype(t_in, [&](auto tin) {
     using Tin = decltype(tin);
     const int mblocks = std::max(1, std::min(64, (p.kg.nu * p.kg.nv + 4095) / 4096));
     if (wcos)
       hipLaunchKernelGGL((k_view_absmax<Tin, true>), dim3(mblocks, nv), dim3(256), 0, s, (const Tin*)img,
-                         p.d_scratch, p.kg, (const float4*)p.d_view, v0);
+                         vmax, p.kg, (const float4*)p.d_view, v0);
     else
       hipLaunchKernelGGL((k_view_absmax<Tin, false>), dim3(mblocks, nv), dim3(256), 0, s, (const Tin*)img,
-                         p.d_scratch, p.kg, (const float4*)p.d_view, v0);
+                         vmax, p.kg, (const float4*)p.d_view, v0);
     hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
     return by_dtype(t_out, [&](auto tout) {
@@ -371,7 +373,7 @@ hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos
 #define DC_SPLAT(W, C)                                                                                         \
   hipLaunchKernelGGL((k_splat<Tin, Tout, W, C>), grid, dim3(512), lds, s, (const Tin*)img, (Tout*)out, p.kg,  \
                      p.d_chunks, p.d_ang, (const float4*)p.d_view, scale, v0, nv, p.n_chunks, p.splat_qmax, \
-                     p.d_scratch)
+                     vmax)
       if (wcos) {
         if (p.splat_checked) DC_SPLAT(true, true); else DC_SPLAT(true, false);
       } else {
