@@ -158,6 +158,17 @@ dc_status dc_plan_grid(dc_plan plan, dc_grid* out);
  * w_cos = D/sqrt(x^2+y^2+D^2).  g float32; R stored as tR. */
 dc_status dc_weight_radon(dc_plan plan, const float* g, void* R, dc_dtype tR,
                           int32_t v0, int32_t nv, hipStream_t stream);
+/* dc_weight_radon for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): the same stage, bit for bit,
+ * with its per-view fixed-point scale words in a static device array of 65536
+ * words (256 KiB) that each GPU holds until the process ends, instead of the
+ * plan's scratch.  Nothing is allocated in the call.  At most 65536 views per
+ * call (DC_ESHAPE beyond).  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other plans, other
+ * threads) race and must be ordered by the caller.  The array is cleared by a
+ * kernel at the start of each call. */
+dc_status dc_weight_radon_noalloc(dc_plan plan, const float* g, void* R, dc_dtype tR,
+                                  int32_t v0, int32_t nv, hipStream_t stream);
 /* Exact transpose of dc_weight_radon: Gg[v] = w_cos (du dv/ds) interp(GR[v]).  Gg float32, overwritten. */
 dc_status dc_weight_radon_adjoint(dc_plan plan, const void* GR, dc_dtype tR, float* Gg,
                                   int32_t v0, int32_t nv, hipStream_t stream);

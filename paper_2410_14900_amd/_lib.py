@@ -69,6 +69,7 @@ SIGNATURES = {
     "dc_plan_n_samples": (_i, [_p]),
     "dc_plan_grid": (_i, [_p, POINTER(DcGrid)]),
     "dc_weight_radon": (_i, [_p, _vp, _vp, _i, _i, _i, _vp]),
+    "dc_weight_radon_noalloc": (_i, [_p, _vp, _vp, _i, _i, _i, _vp]),
     "dc_weight_radon_adjoint": (_i, [_p, _vp, _i, _vp, _i, _i, _vp]),
     "dc_filter": (_i, [_p, _vp, _i, _vp, _i, _vp, _i, _i, _i, _vp]),
     "dc_filter_adjoint": (_i, [_p, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp]),

@@ -181,6 +181,10 @@ static dc_status create(const dc_grid* grid, const dc_view* views, int32_t n_vie
     free_plan(p);
     return st;
   }
+  // set-up of the allocation-free entry point on this device (a failure here is
+  // reported by that entry point, which repeats the lookup)
+  unsigned* words = nullptr;
+  (void)static_scratch(p->device, &words);
   *out = reinterpret_cast<dc_plan>(p);
   return DC_OK;
 }
@@ -249,6 +253,25 @@ dc_status dc_weight_radon(dc_plan plan, const float* g, void* R, dc_dtype tR, in
   const Plan& p = *reinterpret_cast<Plan*>(plan);
   float scale = (float)(p.grid.du * p.grid.dv / p.grid.ds);
   return launched(launch_splat(p, g, DC_F32, true, scale, R, tR, v0, nv, stream), "dc_weight_radon");
+}
+
+dc_status dc_weight_radon_noalloc(dc_plan plan, const float* g, void* R, dc_dtype tR, int32_t v0, int32_t nv,
+                                  hipStream_t stream) {
+  DC_TRY(check_call(plan, v0, nv));
+  DC_TRY(check_ptr(g, "g"));
+  DC_TRY(check_ptr(R, "R"));
+  DC_TRY(check_dtype(tR, "R"));
+  if (nv > kNoAllocViews)
+    return fail(DC_ESHAPE, "dc_weight_radon_noalloc takes at most " + std::to_string(kNoAllocViews) +
+                               " views per call (its static scratch holds one word per view); got " +
+                               std::to_string(nv));
+  if (nv == 0) return DC_OK;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  unsigned* words = nullptr;
+  const hipError_t e = static_scratch(p.device, &words);
+  if (e != hipSuccess) return fail(DC_EHIP, std::string("static scratch address: ") + hipGetErrorString(e));
+  float scale = (float)(p.grid.du * p.grid.dv / p.grid.ds);
+  return launched(launch_splat(p, g, DC_F32, true, scale, R, tR, v0, nv, stream, words), "dc_weight_radon_noalloc");
 }
 
 dc_status dc_weight_radon_adjoint(dc_plan plan, const void* GR, dc_dtype tR, float* Gg, int32_t v0,

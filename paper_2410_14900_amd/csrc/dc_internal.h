@@ -159,6 +159,11 @@ hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 // (nullptr: the plan's scratch)
 hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale,
                         void* out, dc_dtype t_out, int v0, int nv, hipStream_t s, unsigned* vmax_words = nullptr);
+// The allocation-free splat's static scratch (radon2d.hip): kNoAllocViews words per
+// GPU; *out = its address on `device`, which must be current (looked up once per device).
+static constexpr int kNoAllocViews = 65536;
+static constexpr int kMaxDevices = 64;
+hipError_t static_scratch(int device, unsigned** out);
 hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wcos, float scale,
                          void* out, dc_dtype t_out, int v0, int nv, hipStream_t s);
 hipError_t launch_filter(const Plan& p, const void* R, dc_dtype tR, const float* M, int raw,

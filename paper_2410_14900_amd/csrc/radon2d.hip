@@ -7,6 +7,7 @@
 // mu_k, Lambda the hat function and w the optional cosine weight D/sqrt(x^2+y^2+D^2).
 // The two are exact transposes of each other for equal scales.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "dc_internal.h"
@@ -348,6 +349,29 @@ __global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ r
 }
 
 // --------------------------------------------------------------- dispatch
+
+// Scratch of the allocation-free splat entry point (dc_weight_radon_noalloc): one
+// word per view of a call, in a static device array.  Each GPU holds its own copy
+// until the process ends; host code reaches it only through the per-device
+// address from hipGetSymbolAddress (the array's name is a host-side stand-in).
+static __device__ __align__(256) unsigned scratch[kNoAllocViews];
+
+static std::mutex g_scratch_mu;
+static unsigned* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(int device, unsigned** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    // called with `device` current (plan creation, or a call on that device's plan)
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<unsigned*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos, float scale, void* out,
                         dc_dtype t_out, int v0, int nv, hipStream_t s, unsigned* vmax_words) {

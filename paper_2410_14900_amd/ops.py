@@ -144,6 +144,18 @@ def dc_weight_radon(plan, g, R, v0=0, nv=None, stream=None):
     return R
 
 
+def dc_weight_radon_noalloc(plan, g, R, v0=0, nv=None, stream=None):
+    """dc_weight_radon with its scratch in the library's static device array
+    (allocates nothing; calls on one GPU must not overlap)."""
+    V = plan.n_views
+    _need(g, "g", (V,) + plan.det_shape)
+    _need(R, "R", (V,) + plan.sino_shape, ANY)
+    v0, nv = _range(plan, v0, nv)
+    check(_lib.lib().dc_weight_radon_noalloc(plan.handle, _ptr(g), _ptr(R), _DT[R.dtype], v0, nv,
+                                             _stream(stream)), "dc_weight_radon_noalloc")
+    return R
+
+
 def dc_weight_radon_adjoint(plan, GR, Gg, v0=0, nv=None, stream=None):
     V = plan.n_views
     _need(GR, "GR", (V,) + plan.sino_shape, ANY)
