@@ -116,28 +116,81 @@ def stage_work(g, V, bpe_store):
     }
 
 
-def cpu_baseline(grid, views, n_views=1):
-    """Times the float64 oracle on a bounded sample: n_views views of the same
-    step (forward + backward to dL/dM) at full detector, sinogram and volume size."""
+SLABS = 16   # the oracle worker's 3D stages run on one z-slab of 1/SLABS of the volume
+
+
+def _oracle_step(args):
+    """One view's forward + backward step of the float64 oracle (a worker of
+    cpu_baseline), its 3D stages on one z-slab of the volume.  Returns (seconds
+    of the 2D stages, seconds of the 3D stages on the slab)."""
+    grid, sub, slab = args
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import pipeline as O
-    sub = views.subset(list(range(n_views)))
-    rng = np.random.Generator(np.random.PCG64(0))
-    g = rng.uniform(0, 1, (n_views, grid.nv, grid.nu))
-    M = np.full((n_views, grid.n_theta, grid.n_s), 0.5)
+    with threadpool_limits(1):
+        rng = np.random.Generator(np.random.PCG64(0))
+        g = rng.uniform(0, 1, (1, grid.nv, grid.nu))
+        M = np.full((1, grid.n_theta, grid.n_s), 0.5)
+        nz = grid.nz // SLABS
+        zz, yy, xx = np.meshgrid(np.arange(slab * nz, (slab + 1) * nz), np.arange(grid.ny), np.arange(grid.nx),
+                                 indexing="ij")
+        idx = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], axis=1)
+        t0 = time.perf_counter()
+        R = O.weight_radon(g, grid, sub)
+        H = O.filter_stack(R, M, grid, sub)
+        gF = O.detector_bp(H, grid)
+        t1 = time.perf_counter()
+        f = O.cone_bp(gF, grid, sub, relu=True, points=O.voxel_centres(grid, idx))
+        GgF = O.cone_bp_adjoint(f, grid, sub, relu_f=f, support=idx)
+        t2 = time.perf_counter()
+        GH = O.detector_bp_adjoint(GgF, grid)
+        O.filter_stack_adjoint(GH, R, M, grid, sub)
+        t3 = time.perf_counter()
+        return (t1 - t0) + (t3 - t2), t2 - t1
+
+
+def host_cpu():
+    """(usable cores, logical CPUs, model name) of this host."""
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return usable, os.cpu_count(), model
+
+
+def cpu_baseline(grid, views, max_workers=16):
+    """Times the float64 oracle on a bounded sample of the same step: one worker
+    process per usable host core (at most max_workers, BLAS held to one thread
+    each), all running at once.  Each runs one view's forward + backward (views
+    spread over the orbit) with the 2D stages at full size and the two 3D stages
+    on one z-slab of 1/16 of the 256^3 volume (their work is linear in the voxel
+    count), so a worker's step time for a whole view is t_2D + 16 t_slab.  Run
+    before the GPU is touched, so the workers are plain forks."""
+    import multiprocessing as mp
+    usable, logical, model = host_cpu()
+    W = max(1, min(max_workers, usable))
+    picks = [int(round(i * len(views) / W)) % len(views) for i in range(W)]
+    jobs = [(grid, views.subset([v]), i % SLABS) for i, v in enumerate(picks)]
     t0 = time.perf_counter()
-    R = O.weight_radon(g, grid, sub)
-    H = O.filter_stack(R, M, grid, sub)
-    gF = O.detector_bp(H, grid)
-    f = O.cone_bp(gF, grid, sub, relu=True)
-    GgF = O.cone_bp_adjoint(f, grid, sub, relu_f=f)
-    GH = O.detector_bp_adjoint(GgF, grid)
-    O.filter_stack_adjoint(GH, R, M, grid, sub)
-    dt = time.perf_counter() - t0
+    with mp.get_context("fork").Pool(W) as pool:
+        per = pool.map(_oracle_step, jobs)
+    wall = time.perf_counter() - t0
     nvox = grid.nx * grid.ny * grid.nz
-    return {"value": nvox * n_views / dt, "unit": "voxel-view updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d views of the same forward+backward step (full 512^2 detector, 360x725 sinogram, "
-                      "256^3 volume), float64 NumPy, single thread; %.1f s" % (n_views, len(views), dt)}
+    step = [t2d + SLABS * t3d for t2d, t3d in per]           # seconds per whole view, per worker
+    rate = sum(nvox / t for t in step)                         # all workers together
+    return {"value": rate, "unit": "voxel-view updates/s", "cores": W, "kind": "oracle",
+            "host": {"usable_cores": usable, "logical_cpus": logical, "cpu_model": model},
+            "sample": "%d worker processes at once (BLAS 1 thread each), each one view of the same forward+backward "
+                      "step: 2D stages at full size (512^2 detector, 360x725 sinogram), the 3D stages on a 1/%d z-slab "
+                      "of the 256^3 volume scaled by %d; float64 NumPy; %.1f s wall; per view %.1f s (2D %.1f s + 3D "
+                      "%.1f s)" % (W, SLABS, SLABS, wall, sum(step) / W, sum(p[0] for p in per) / W,
+                                   SLABS * sum(p[1] for p in per) / W)}
 
 
 def adam_(M, G, m, v, t, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8):
@@ -275,13 +328,18 @@ def batched_c4(P, synth, args):
         targets.append(synth.voxelize_torch(ell, grid, device="cuda"))
     Vt = sum(len(v) for v in sets)
     log("C4 inputs ready:", [len(v) for v in sets], "views")
-    singles = [Trainer(P, P.Plan(grid, v), g, t, torch.float32) for v, g, t in zip(sets, gs, targets)]
+    plans = [P.Plan(grid, v) for v in sets]
+    if not args.no_autotune:
+        for pl in plans:
+            pl.autotune()
+    singles = [Trainer(P, pl, g, t, torch.float32) for pl, g, t in zip(plans, gs, targets)]
     ms32, _ = time_eager(singles, args.batched_steps, args.warmup)
     err32 = sum(tr.rel_error() for tr in singles) / len(singles)
     log("C4 fp32 per-scan eager: %.2f ms/step, mean relative error %.5f" % (ms32, err32))
-    del singles
+    del singles, plans
     torch.cuda.empty_cache()
     plan = P.Plan.batched(grid, sets)
+    batched_knobs = plan.autotune()["knobs"] if not args.no_autotune else plan.knobs()
     g = torch.cat(gs)
     del gs
     tb = Trainer(P, plan, g, torch.stack(targets), torch.bfloat16)
@@ -300,8 +358,71 @@ def batched_c4(P, synth, args):
         "bf16_batched_graph": {"value": nvox * Vt / (msbg * 1e-3), "ms_per_step": round(msbg, 3),
                                "mean_rel_error": round(errbg, 6)},
         "speedup": round(ms32 / msbg, 3),
+        "batched_knobs": batched_knobs,
         "steps": args.batched_steps,
     }
+
+
+def c3_line(P, synth, args):
+    """The circle-plus-arc workload (C3: 100 arc views at +-30 degrees, then 360
+    circle views; the C2 grid), the same training step in FP32 and in BF16
+    storage, eagerly."""
+    import torch
+    c = synth.CONFIGS["C3"]
+    grid, views = synth.config_geometry("C3")
+    ell = synth.random_ellipsoids(c["n_ell"], grid.nx * grid.vx, c["seed"])
+    g = synth.project_ellipsoids(ell, grid, views, device="cuda").float().contiguous()
+    target = synth.voxelize_torch(ell, grid, device="cuda")
+    plan = P.Plan(grid, views)
+    knobs = plan.autotune() if not args.no_autotune else {"knobs": plan.knobs()}
+    V, nvox = len(views), grid.nx * grid.ny * grid.nz
+    out = {"knobs": knobs["knobs"], "workload": "C3: circle+arc orbit, 100 arc views (+-30 deg) then 360 circle views, 512x512 detector "
+                       "@0.6 mm, Radon 360x725, 256^3 volume @0.5 mm, forward+backward w.r.t. M + Adam step",
+           "views": V}
+    for store, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        tr = Trainer(P, plan, g, target, dt)
+        ms, kern = time_eager([tr], args.steps, args.warmup, per_stage=True)
+        out[store] = {"value": nvox * V / (ms * 1e-3), "ms_per_step": round(ms, 3),
+                      "kernels_ms": {k: round(v, 3) for k, v in kern.items()}, "rel_error": round(tr.rel_error(), 6)}
+        log("C3 %s: %.2f ms/step" % (store, ms), json.dumps(out[store]["kernels_ms"]))
+        del tr
+        torch.cuda.empty_cache()
+    return out
+
+
+def c5_line(P, synth, args):
+    """The full C-arm scale workload (C5: 512^3 at 0.25 mm, 976^2 detector at
+    0.308 mm, Radon 720 x 1381, 496-view sinusoid): the training step with FP16
+    storage of the filtered sinograms and detector images, the Radon stack
+    recomputed every step, with the plan's default knobs and with the autotuner's."""
+    import torch
+    c = synth.CONFIGS["C5"]
+    grid, views = synth.config_geometry("C5")
+    ell = synth.random_ellipsoids(c["n_ell"], grid.nx * grid.vx, c["seed"])
+    g = synth.project_ellipsoids(ell, grid, views, device="cuda").float().contiguous()
+    target = synth.voxelize_torch(ell, grid, device="cuda")
+    plan = P.Plan(grid, views)
+    V, nvox = len(views), grid.nx * grid.ny * grid.nz
+    out = {"workload": "C5: sinusoidal orbit, 496 views, 976x976 detector @0.308 mm, Radon 720x1381, 512^3 volume "
+                       "@0.25 mm, FP16 storage, Radon stack recomputed every step, forward+backward + Adam step",
+           "views": V, "default_knobs": plan.knobs()}
+    steps, warm = max(2, args.steps // 2), 1
+    tr = Trainer(P, plan, g, target, torch.float16)
+    ms, kern = time_eager([tr], steps, warm, per_stage=True)
+    out["default"] = {"value": nvox * V / (ms * 1e-3), "ms_per_step": round(ms, 3),
+                      "kernels_ms": {k: round(v, 3) for k, v in kern.items()}}
+    log("C5 default knobs: %.2f ms/step" % ms, json.dumps(out["default"]["kernels_ms"]))
+    if not args.no_autotune:
+        out["tuned_knobs"] = plan.autotune()
+        ms, kern = time_eager([tr], steps, warm, per_stage=True)
+        out["tuned"] = {"value": nvox * V / (ms * 1e-3), "ms_per_step": round(ms, 3),
+                        "kernels_ms": {k: round(v, 3) for k, v in kern.items()}}
+        log("C5 tuned knobs %s: %.2f ms/step" % (json.dumps(out["tuned_knobs"]["knobs"]), ms),
+            json.dumps(out["tuned"]["kernels_ms"]))
+    out["rel_error"] = round(tr.rel_error(), 6)
+    del tr
+    torch.cuda.empty_cache()
+    return out
 
 
 def crofton_baseline(P, plan, views, g, target):
@@ -348,8 +469,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", choices=["f32", "bf16", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=4)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="largest number of oracle worker processes (one per usable core up to this)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 8-scan measurement")
+    ap.add_argument("--no-c3", action="store_true", help="skip the circle-plus-arc (C3) line")
+    ap.add_argument("--no-c5", action="store_true", help="skip the full C-arm scale (C5) line")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plans' default knobs")
     ap.add_argument("--orbit", choices=["sinusoid", "circle"], default="sinusoid",
                     help="the C2 grid on its sinusoidal orbit (default) or on a 496-view circle")
     ap.add_argument("--batched-steps", type=int, default=3)
@@ -361,8 +486,16 @@ def main():
               "with one all-reduce of the volume, which is not built).", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import synth
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle first, in forked worker processes, before anything touches the GPU
+        g_c2, v_c2 = synth.config_geometry("C2")
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(g_c2, v_c2, args.cpu_workers)
+        log("cpu baseline:", json.dumps(cpu))
+
+    import torch
     import paper_2410_14900_amd as P
 
     if not torch.cuda.is_available():
@@ -406,6 +539,16 @@ def main():
         del src, dst
     torch.cuda.synchronize()
     log("inputs ready")
+    # the step with the plan's default knobs, then the autotuner's choice (used below)
+    tr = Trainer(P, plan, g, target, torch.float32)
+    default_ms, _ = time_eager([tr], args.steps, args.warmup)
+    del tr
+    tuned = {"default_knobs": plan.knobs(), "default_knobs_ms_per_step": round(default_ms, 3)}
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuned.update(plan.autotune())
+        tuned["tune_s"] = round(time.perf_counter() - t0, 3)
+    log("knobs:", json.dumps(tuned))
 
     results = {}
     for store in (["f32", "bf16"] if args.dtype == "both" else [args.dtype]):
@@ -484,6 +627,7 @@ def main():
                                "256^3 volume @0.5 mm, forward+backward w.r.t. M + Adam step",
                    "views": V, "detector": [grid.nv, grid.nu], "radon": [grid.n_theta, grid.n_s],
                    "volume": [grid.nz, grid.ny, grid.nx]},
+        "knobs": tuned,
         "roofline": roof,
         "kernels": r["per_kernel"],
         "rel_error": round(r["rel_error"], 6),
@@ -499,13 +643,21 @@ def main():
     if graph_ms is not None:
         out["bf16_graph"] = {"value": nvox * V / (graph_ms * 1e-3), "ms_per_step": round(graph_ms, 3),
                              "speedup_vs_f32": round(r["ms"] / graph_ms, 3) if main_store == "f32" else None}
-    if not args.no_batched:
+    if not args.no_c3:
+        out["c3"] = c3_line(P, synth, args)
+        torch.cuda.empty_cache()
+    if not args.no_c5:
         del plan
         torch.cuda.empty_cache()
+        out["c5"] = c5_line(P, synth, args)
+        torch.cuda.empty_cache()
+        plan = None
+    if not args.no_batched:
+        plan = None
+        torch.cuda.empty_cache()
         out["batched"] = batched_c4(P, synth, args)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(grid, views, args.cpu_views)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
         out["crofton_weight"]["oracle_entries_per_s"] = round(crofton_oracle_rate(grid, views), 1)
     print(json.dumps(out), flush=True)
 

@@ -119,6 +119,50 @@ dc_status dc_plan_create_batched(const dc_grid* grid, const dc_view* views, int3
                                  dc_plan* out);
 dc_status dc_plan_destroy(dc_plan plan);
 
+/* Work shapes of the kernels (the plan's knobs).  Every value gives the same
+ * results up to float32 rounding: splat_angles, fp_tile_u (integer sums) and
+ * interp_angles (the same sums in the same order) give bit-identical outputs;
+ * interp_tile_u changes the float32 rounding of pixel positions, and bp_block_y
+ * that of the cone BP only where one block's detector footprint is too large to
+ * stage in LDS and its taps take the direct form.
+ *   splat_angles   sinogram rows one weighted-Radon / detector-Radon workgroup holds
+ *                  in LDS, 1..8 (0 on input: as many as fit 80 KiB);
+ *   interp_tile_u  detector-BP pixel tile width, 32 or 64 (tile height 64);
+ *   interp_angles  detector-BP angles staged per chunk, 16, 32 or 64;
+ *   bp_block_y     cone-BP voxel block rows, 16 or 32 (block 16 x rows x 8);
+ *   fp_tile_u      cone-FP detector tile width, 16, 20 or 24 (tile height 64).
+ * A plan starts with 0 / 64 / 32 / 32 / 20, the values tuned by hand on the
+ * 256^3 volume, 512^2 detector, 360 x 725 sinogram workload. */
+typedef struct {
+  int32_t splat_angles, interp_tile_u, interp_angles, bp_block_y, fp_tile_u;
+} dc_knobs;
+dc_status dc_plan_get_knobs(dc_plan plan, dc_knobs* out);
+/* Re-derives the plan's tables for other knobs.  DC_EINVAL for a value the
+ * kernels are not built for, DC_ENOTSUP when the geometry does not fit it (LDS);
+ * the plan is unchanged on failure.  Allocates, and synchronises the device before
+ * releasing the old tables: call it, like dc_plan_create, outside stream capture
+ * and with no stage call on this plan in flight on another thread. */
+dc_status dc_plan_set_knobs(dc_plan plan, const dc_knobs* knobs);
+/* The autotuner: times every candidate value of each knob on the plan's own
+ * geometry and sets the fastest.  Each stage is timed (on `stream`, one warm-up and
+ * three timed runs, the fastest kept) over up to four runs of 8 consecutive views
+ * spread over the plan, on seeded synthetic inputs in temporary device buffers
+ * allocated and freed inside the call: dc_weight_radon for splat_angles,
+ * dc_detector_bp for interp_tile_u x interp_angles, dc_cone_bp for bp_block_y and
+ * dc_cone_bp_adjoint (with a ReLU mask) for fp_tile_u.
+ *   - DCFBP_KNOBS (environment), e.g. "splat=7,itile=64,iangles=32,bprows=32,fptile=20":
+ *     these knobs are set without timing (unnamed ones keep their current value);
+ *   - DCFBP_TUNE_CACHE (environment): a text file of earlier results, one line per
+ *     geometry key (a 64-bit hash of the grid, every view, the scan split, the GPU's
+ *     architecture name and compute-unit count); a hit sets the cached knobs without
+ *     timing, a miss tunes and appends a line.
+ * *chosen (nullable) receives the knobs set; ms (nullable, 4 doubles) the chosen
+ * knobs' measured times of the four stages over the sampled views (0 when not
+ * timed).  *source (nullable) is set to 0 (timed), 1 (cache) or 2 (environment).
+ * Synchronises the device; call it outside stream capture.  flags must be 0. */
+dc_status dc_plan_autotune(dc_plan plan, uint32_t flags, hipStream_t stream, dc_knobs* chosen, double* ms,
+                           int32_t* source);
+
 /* The bounds and kernel forms a plan over these views would use, computed on the
  * host only (no device, no allocation): the same float64 derivation as
  * dc_plan_create, for a one-scan plan.  They decide the safety and accuracy of

@@ -42,6 +42,11 @@ class DcOrbitSegment(ctypes.Structure):
 DC_SEG_CIRCLE, DC_SEG_ARC, DC_SEG_LINE, DC_SEG_SINUSOID = 1, 2, 3, 4
 
 
+class DcKnobs(ctypes.Structure):
+    _fields_ = [("splat_angles", c_int32), ("interp_tile_u", c_int32), ("interp_angles", c_int32),
+                ("bp_block_y", c_int32), ("fp_tile_u", c_int32)]
+
+
 class DcBounds(ctypes.Structure):
     _fields_ = [("splat_angles", c_int32), ("splat_max_terms", c_int32), ("splat_checked", c_int32),
                 ("interp_window", c_int32), ("interp_local", c_int32), ("cone_max_terms", c_int32),
@@ -64,6 +69,9 @@ SIGNATURES = {
                                    POINTER(c_void_p)]),
     "dc_plan_destroy": (_i, [_p]),
     "dc_plan_bounds": (_i, [POINTER(DcGrid), POINTER(DcView), _i, POINTER(DcBounds)]),
+    "dc_plan_get_knobs": (_i, [_p, POINTER(DcKnobs)]),
+    "dc_plan_set_knobs": (_i, [_p, POINTER(DcKnobs)]),
+    "dc_plan_autotune": (_i, [_p, c_uint32, _vp, POINTER(DcKnobs), POINTER(c_double), POINTER(c_int32)]),
     "dc_last_error": (c_char_p, []),
     "dc_plan_n_views": (_i, [_p]),
     "dc_plan_n_samples": (_i, [_p]),

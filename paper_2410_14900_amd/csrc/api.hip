@@ -27,14 +27,31 @@ static dc_status validate(const dc_grid* g, const dc_view* views, int32_t n) {
   return st;
 }
 
-KernelShape kernel_shape() {
+
+// Derives the plan's tables for shape ks and uploads them (replacing any earlier
+// tables of the plan): plan creation and knob changes.
+static dc_status upload_tables(Plan* p, const dc_view* views, const KernelShape& ks);
+
+dc_status set_shape(Plan* p, const KernelShape& ks) { return upload_tables(p, p->views.data(), ks); }
+
+KernelShape shape_of(const dc_knobs& k) {
   KernelShape ks;
-  ks.interp_tx = interp_tile(0);
-  ks.interp_ty = interp_tile(1);
-  ks.bp_bx = cone_bp_block(0);
-  ks.bp_by = cone_bp_block(1);
-  ks.bp_bz = cone_bp_block(2);
+  ks.splat_kc = k.splat_angles;
+  ks.interp_tx = k.interp_tile_u;
+  ks.interp_kc = k.interp_angles;
+  ks.bp_by = k.bp_block_y;
+  ks.fp_ti = k.fp_tile_u;
   return ks;
+}
+
+dc_knobs knobs_of(const KernelShape& ks) {
+  dc_knobs k{};
+  k.splat_angles = ks.splat_kc;
+  k.interp_tile_u = ks.interp_tx;
+  k.interp_angles = ks.interp_kc;
+  k.bp_block_y = ks.bp_by;
+  k.fp_tile_u = ks.fp_ti;
+  return k;
 }
 
 static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, const int32_t* first,
@@ -49,10 +66,62 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
   k.du = (float)g->du; k.dv = (float)g->dv; k.ds = (float)g->ds;
   k.cu = 0.5f * (g->nu - 1); k.cv = 0.5f * (g->nv - 1);
 
+  p->views.assign(views, views + n);
+  const dc_status st = upload_tables(p, views, KernelShape());
+  if (st != DC_OK) return st;
+  hipError_t e;
+  if ((e = hipMalloc((void**)&p->d_scratch, (n + n_samples) * sizeof(unsigned))) != hipSuccess ||
+      (e = hipMalloc((void**)&p->d_masked, (size_t)n_samples * g->nx * g->ny * g->nz * sizeof(float))) !=
+          hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP, std::string("plan scratch: ") + hipGetErrorString(e));
+  return DC_OK;
+}
+
+static dc_status upload_tables(Plan* p, const dc_view* views, const KernelShape& ks) {
+  const dc_grid* g = &p->grid;
+  const int n = p->n_views, n_samples = p->n_samples;
   HostPlan hp;
   std::string err;
-  const dc_status st = plan_tables(g, views, n, first, n_samples, kernel_shape(), &hp, &err);
+  const dc_status st = plan_tables(g, views, n, p->first.data(), n_samples, ks, &hp, &err);
   if (st != DC_OK) return fail(st, err);
+  // upload into new buffers; the plan keeps its old tables unless all succeed
+  enum { kAng, kTrig, kView, kFrame, kProj, kRmax2, kChunks, kFirst, kN };
+  void* fresh[kN] = {};
+  const void* src[kN] = {hp.ang.data(), hp.trig.data(), hp.vf.data(), hp.frame.data(),
+                         hp.proj.data(), hp.rmax2.data(), hp.chunks.data(), p->first.data()};
+  const size_t bytes[kN] = {hp.ang.size() * sizeof(double), hp.trig.size() * sizeof(float),
+                            hp.vf.size() * sizeof(float), hp.frame.size() * sizeof(double),
+                            hp.proj.size() * sizeof(double), hp.rmax2.size() * sizeof(float),
+                            hp.chunks.size() * sizeof(int), p->first.size() * sizeof(int)};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < kN && e == hipSuccess; ++i) {
+    e = hipMalloc(&fresh[i], bytes[i]);
+    if (e == hipSuccess) e = hipMemcpy(fresh[i], src[i], bytes[i], hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    for (void* q : fresh)
+      if (q) (void)hipFree(q);
+    return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP, std::string("plan upload: ") + hipGetErrorString(e));
+  }
+  // the old tables may still be read by queued kernels: let the device drain first
+  void* old[kN] = {p->d_ang, p->d_trig, p->d_view, p->d_frame, p->d_proj, p->d_rmax2, p->d_chunks, p->d_first};
+  bool any_old = false;
+  for (void* q : old) any_old = any_old || q;
+  if (any_old) {
+    (void)hipDeviceSynchronize();
+    for (void* q : old)
+      if (q) (void)hipFree(q);
+  }
+  p->d_ang = (double*)fresh[kAng];
+  p->d_trig = (float*)fresh[kTrig];
+  p->d_view = (float*)fresh[kView];
+  p->d_frame = (double*)fresh[kFrame];
+  p->d_proj = (double*)fresh[kProj];
+  p->d_rmax2 = (float*)fresh[kRmax2];
+  p->d_chunks = (int4*)fresh[kChunks];
+  p->d_first = (int*)fresh[kFirst];
+  p->shape = ks;
+  p->shape.splat_kc = hp.splat_kc;
   p->interp_wl = hp.interp_wl;
   p->splat_kc = hp.splat_kc;
   p->splat_max_terms = hp.splat_max_terms;
@@ -63,26 +132,6 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
   p->cone_form = hp.cone_form;
   p->splat_qmax = fixed_point_qmax(hp.splat_max_terms);
   p->cone_qmax = fixed_point_qmax(hp.cone_max_terms);
-
-  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
-    hipError_t e = hipMalloc(dst, bytes);
-    if (e != hipSuccess) return e;
-    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-  };
-  hipError_t e;
-  if ((e = up((void**)&p->d_ang, hp.ang.data(), hp.ang.size() * sizeof(double))) != hipSuccess ||
-      (e = up((void**)&p->d_trig, hp.trig.data(), hp.trig.size() * sizeof(float))) != hipSuccess ||
-      (e = up((void**)&p->d_view, hp.vf.data(), hp.vf.size() * sizeof(float))) != hipSuccess ||
-      (e = up((void**)&p->d_frame, hp.frame.data(), hp.frame.size() * sizeof(double))) != hipSuccess ||
-      (e = up((void**)&p->d_proj, hp.proj.data(), hp.proj.size() * sizeof(double))) != hipSuccess ||
-      (e = up((void**)&p->d_rmax2, hp.rmax2.data(), hp.rmax2.size() * sizeof(float))) != hipSuccess ||
-      (e = up((void**)&p->d_chunks, hp.chunks.data(), hp.chunks.size() * sizeof(int))) != hipSuccess ||
-      (e = up((void**)&p->d_first, p->first.data(), p->first.size() * sizeof(int))) != hipSuccess ||
-      (e = hipMalloc((void**)&p->d_scratch, (n + n_samples) * sizeof(unsigned))) != hipSuccess ||
-      (e = hipMalloc((void**)&p->d_masked, (size_t)n_samples * g->nx * g->ny * g->nz * sizeof(float))) !=
-          hipSuccess)
-    return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP,
-                std::string("plan upload: ") + hipGetErrorString(e));
   return DC_OK;
 }
 
@@ -168,9 +217,10 @@ static dc_status create(const dc_grid* grid, const dc_view* views, int32_t n_vie
   for (int s = 0; s < n_samples; ++s)
     if (first[s + 1] <= first[s])
       return fail(DC_ESHAPE, "sample " + std::to_string(s) + " has no views (first_view must increase)");
-  if ((long long)((grid->nz + cone_bp_block(2) - 1) / cone_bp_block(2)) * n_samples > 65535)
+  const int bz = KernelShape().bp_bz;
+  if ((long long)((grid->nz + bz - 1) / bz) * n_samples > 65535)
     return fail(DC_ENOTSUP, "too many samples for this volume depth (the backprojection grid holds "
-                            "(nz / " + std::to_string(cone_bp_block(2)) + ") x samples <= 65535 blocks)");
+                            "(nz / " + std::to_string(bz) + ") x samples <= 65535 blocks)");
   Plan* p = new Plan();
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
@@ -206,7 +256,7 @@ dc_status dc_plan_bounds(const dc_grid* grid, const dc_view* views, int32_t n_vi
   HostPlan hp;
   std::string err;
   const int32_t first[2] = {0, n_views};
-  const dc_status st = plan_tables(grid, views, n_views, first, 1, kernel_shape(), &hp, &err);
+  const dc_status st = plan_tables(grid, views, n_views, first, 1, KernelShape(), &hp, &err);
   if (st != DC_OK) return fail(st, err);
   dc_bounds b{};
   b.splat_angles = hp.splat_kc;
@@ -219,13 +269,40 @@ dc_status dc_plan_bounds(const dc_grid* grid, const dc_view* views, int32_t n_vi
   b.cone_form = hp.cone_form[0];
   b.splat_qmax = fixed_point_qmax(hp.splat_max_terms);
   b.cone_qmax = fixed_point_qmax(hp.cone_max_terms);
-  b.bp_block[0] = cone_bp_block(0);
-  b.bp_block[1] = cone_bp_block(1);
-  b.bp_block[2] = cone_bp_block(2);
-  b.interp_tile[0] = interp_tile(0);
-  b.interp_tile[1] = interp_tile(1);
+  const KernelShape ks;
+  b.bp_block[0] = ks.bp_bx;
+  b.bp_block[1] = ks.bp_by;
+  b.bp_block[2] = ks.bp_bz;
+  b.interp_tile[0] = ks.interp_tx;
+  b.interp_tile[1] = ks.interp_ty;
   *out = b;
   return DC_OK;
+}
+
+dc_status dc_plan_get_knobs(dc_plan plan, dc_knobs* out) {
+  if (!plan || !out) return fail(DC_EINVAL, "null argument");
+  *out = knobs_of(reinterpret_cast<Plan*>(plan)->shape);
+  return DC_OK;
+}
+
+dc_status dc_plan_set_knobs(dc_plan plan, const dc_knobs* knobs) {
+  if (!plan || !knobs) return fail(DC_EINVAL, "null argument");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(DC_EINVAL, "current HIP device differs from the plan's device");
+  return set_shape(p, shape_of(*knobs));
+}
+
+dc_status dc_plan_autotune(dc_plan plan, uint32_t flags, hipStream_t stream, dc_knobs* chosen, double* ms,
+                           int32_t* source) {
+  if (!plan) return fail(DC_EINVAL, "null plan");
+  if (flags != 0) return fail(DC_EINVAL, "flags must be 0");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(DC_EINVAL, "current HIP device differs from the plan's device");
+  return autotune(p, stream, chosen, ms, source);
 }
 
 dc_status dc_plan_destroy(dc_plan plan) {

@@ -24,8 +24,8 @@
 
 namespace dc {
 
-static constexpr int kBX = 16, kBY = 32, kZC = 8;
-static constexpr int kBPThreads = kBX * kBY;   // 512
+// Block: kBX x BY x kZC voxels, BY = 16 or 32 (the plan's knob), kBX BY threads.
+static constexpr int kBX = 16, kZC = 8;
 static constexpr float kRoundMagic = 12582912.0f;         // 1.5 * 2^23
 static constexpr unsigned kRoundMagicBits = 0x4B400000u;  // its bit pattern
 
@@ -144,10 +144,11 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
 // STAGE = staged pixels per thread and view (the plan picks the smallest that
 // holds the largest footprint); STAGE == 0 selects direct global taps.  FORM
 // (staged form only) is the plan's choice for the sample (ConeForm).
-template <typename T, int STAGE, int FORM>
-__global__ __launch_bounds__(kBPThreads) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
+template <typename T, int STAGE, int FORM, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
                                                  int nv, const int* __restrict__ first, int s_lo, int nzb) {
+  constexpr int kBPThreads = kBX * BY;
   constexpr int kTile = STAGE > 0 ? kBPThreads * STAGE : 1;
   __shared__ float tile[2][kTile];
   const int tid = threadIdx.y * kBX + threadIdx.x;
@@ -160,8 +161,8 @@ __global__ __launch_bounds__(kBPThreads) void k_cone_bp(const T* __restrict__ gF
     nv = max(0, ve - vb);
   }
   f += (size_t)smp * g.nx * g.ny * g.nz;
-  const int bx0 = blockIdx.x * kBX, by0 = blockIdx.y * kBY, bz0 = zb * kZC;
-  const int bx1 = min(g.nx, bx0 + kBX) - 1, by1 = min(g.ny, by0 + kBY) - 1, bz1 = min(g.nz, bz0 + kZC) - 1;
+  const int bx0 = blockIdx.x * kBX, by0 = blockIdx.y * BY, bz0 = zb * kZC;
+  const int bx1 = min(g.nx, bx0 + kBX) - 1, by1 = min(g.ny, by0 + BY) - 1, bz1 = min(g.nz, bz0 + kZC) - 1;
   const int ix = bx0 + threadIdx.x, iy = by0 + threadIdx.y, iz0 = bz0;
   float acc[kZC];
 #pragma unroll
@@ -355,8 +356,9 @@ __global__ __launch_bounds__(kBPThreads) void k_cone_bp(const T* __restrict__ gF
 // the ReLU mask once into the plan's volume buffer) and the per-view bound on
 // (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
 // box can reach the tile's window are scanned.
-static constexpr int kFTI = 20, kFTJ = 64, kFZS = 16, kFROWS = 512;
-static constexpr int kFW = kFTI + 1, kFH = kFTJ + 1;
+// Tile: TI x kFTJ pixels, TI = 16, 20 or 24 (the plan's knob).
+static constexpr int kFTJ = 64, kFZS = 16, kFROWS = 512;
+static constexpr int kFH = kFTJ + 1;
 
 __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
   // inclusive Hillis-Steele over 256 threads in LDS, returns the exclusive prefix
@@ -423,7 +425,7 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
 // FORM (ConeForm) as in the backprojection; with kConeZinv each (segment, view)
 // has one u, one tap column and one weight, and a segment whose column misses
 // the tile is skipped whole.
-template <typename Tout, bool CLAMP, int FORM>
+template <typename Tout, bool CLAMP, int FORM, int TI>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
                                                  const double* __restrict__ proj, const float* __restrict__ rmax2,
                                                  int v0, int nv, int tiles_u, int n_tiles, float qmax,
@@ -436,6 +438,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   __shared__ int sCount, sNL;
   __shared__ unsigned char sLayerOn[kFMaxLayers];
   __shared__ int sLayer[kFMaxLayers];
+  constexpr int kFTI = TI, kFW = TI + 1;
   __shared__ unsigned long long sAB[kFV][kFW * kFH], sCE[kFV][kFW * kFH];
   // XCD-aware order: workgroup b runs on XCD b % 8; each XCD takes every 8th
   // tile and sweeps it through all view groups, so the ~100 workgroups resident
@@ -610,10 +613,14 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
         for (int z = 0; z < kFZS; ++z) gv[z] = z < nzv ? gv[z] : 0.f;
       } else {
         // slices past the last one lie past the end of the volume and read 0
-        const unsigned base = 4u * (unsigned)off, step = 4u * (unsigned)plane;
+        // byte offsets advanced by one add per slice (the slice step is uniform)
+        unsigned a = 4u * (unsigned)off;
+        const unsigned step = 4u * (unsigned)plane;
 #pragma unroll
-        for (int z = 0; z < kFZS; ++z)
-          gv[z] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(vol, (int)(base + z * step), 0, 0));
+        for (int z = 0; z < kFZS; ++z) {
+          gv[z] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(vol, (int)a, 0, 0));
+          a += step;
+        }
       }
       for (int w = 0; w < nvw; ++w) {
         const float Sw = pick(S, w);
@@ -738,12 +745,18 @@ hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, 
 
 static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0,
                                      int nv, int s_lo, int s_hi, int nzb, int form, hipStream_t s) {
-  dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + kBY - 1) / kBY, nzb * (s_hi - s_lo + 1));
+  const int BYr = p.shape.bp_by;
+  dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + BYr - 1) / BYr, nzb * (s_hi - s_lo + 1));
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
-#define DC_BP(ST, Z)                                                                                          \
-  hipLaunchKernelGGL((k_cone_bp<T, ST, Z>), grid, dim3(kBX, kBY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, \
+#define DC_BP1(ST, Z, BY)                                                                                           \
+  hipLaunchKernelGGL((k_cone_bp<T, ST, Z, BY>), grid, dim3(kBX, BY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, \
                      relu, v0, nv, p.d_first, s_lo, nzb)
+#define DC_BP(ST, Z)                   \
+  do {                                 \
+    if (BYr == 16) DC_BP1(ST, Z, 16);  \
+    else DC_BP1(ST, Z, 32);            \
+  } while (0)
 #define DC_BP_FORMS(ST)                                            \
   switch (form) {                                                  \
     case kConeZinv: DC_BP(ST, kConeZinv); break;                   \
@@ -759,16 +772,15 @@ static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF,
     }
 #undef DC_BP_FORMS
 #undef DC_BP
+#undef DC_BP1
     return hipGetLastError();
   });
 }
 
-int cone_bp_block(int axis) { return axis == 0 ? kBX : axis == 1 ? kBY : kZC; }
-int cone_bp_threads() { return kBPThreads; }
-
 hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, void* GgF, dc_dtype tF, int v0,
                           int nv, hipStream_t s) {
-  const int tiles_u = (p.kg.nu + kFTI - 1) / kFTI, tiles_v = (p.kg.nv + kFTJ - 1) / kFTJ;
+  const int TIr = p.shape.fp_ti;
+  const int tiles_u = (p.kg.nu + TIr - 1) / TIr, tiles_v = (p.kg.nv + kFTJ - 1) / kFTJ;
   int s_lo, s_hi;
   sample_span(p, v0, nv, &s_lo, &s_hi);
   const int n_smp = s_hi - s_lo + 1;
@@ -796,9 +808,15 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
       }
       if (ng > 0) {
         const dim3 grid(8 * ((n_tiles + 7) / 8) * ng);
-#define DC_FP(C, Z)                                                                                              \
-  hipLaunchKernelGGL((k_cone_fp<T, C, Z>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, nv, \
-                     tiles_u, n_tiles, p.cone_qmax, gmax, p.d_first, a, b, ng)
+#define DC_FP1(C, Z, TI)                                                                                        \
+  hipLaunchKernelGGL((k_cone_fp<T, C, Z, TI>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, \
+                     nv, tiles_u, n_tiles, p.cone_qmax, gmax, p.d_first, a, b, ng)
+#define DC_FP(C, Z)                                  \
+  do {                                               \
+    if (TIr == 16) DC_FP1(C, Z, 16);                 \
+    else if (TIr == 24) DC_FP1(C, Z, 24);            \
+    else DC_FP1(C, Z, 20);                           \
+  } while (0)
         const bool clamp = top >= 4294967296.0;
         switch (p.cone_form[a]) {
           case kConeZinv: if (clamp) DC_FP(true, kConeZinv); else DC_FP(false, kConeZinv); break;
@@ -806,6 +824,7 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
           default: if (clamp) DC_FP(true, kConeGeneral); else DC_FP(false, kConeGeneral); break;
         }
 #undef DC_FP
+#undef DC_FP1
         const hipError_t e2 = hipGetLastError();
         if (e2 != hipSuccess) return e2;
       }

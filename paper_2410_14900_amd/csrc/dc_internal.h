@@ -97,18 +97,24 @@ struct Plan {
   // fixed-point scales: a sum of the splat (cone FP) holds terms of at most qmax
   // units, qmax = fixed_point_qmax(splat_max_terms (cone_max_terms))
   float splat_qmax = 0.f, cone_qmax = 0.f;
+  // the kernels' work shapes (knobs) the tables were derived for
+  KernelShape shape;
+  // host copy of the views, to re-derive the tables for another shape
+  std::vector<dc_view> views;
 };
 
-// Kernel shapes the plan's bounds are derived for (api.hip).
-KernelShape kernel_shape();
+
 
 void set_error(const std::string& msg);
 
-// backprojection voxel block edge along axis 0/1/2 (cone.hip)
-int cone_bp_block(int axis);
-int cone_bp_threads();   // threads per backprojection workgroup
-// pixel tile of the detector-BP (interpolation) kernel along u (axis 0) and v (axis 1)
-int interp_tile(int axis);
+// Re-derives and uploads the plan's tables for another kernel shape (api.hip);
+// synchronises the device before freeing the old tables.
+dc_status set_shape(Plan* p, const KernelShape& ks);
+KernelShape shape_of(const dc_knobs& k);
+dc_knobs knobs_of(const KernelShape& ks);
+// dc_plan_autotune's search (autotune.hip)
+dc_status autotune(Plan* p, hipStream_t s, dc_knobs* chosen, double* ms, int32_t* source);
+
 static constexpr int kInterpLocalAbove = 160;
 
 // samples whose views meet [v0, v0+nv): s_lo..s_hi; for an empty range the

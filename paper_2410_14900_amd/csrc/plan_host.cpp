@@ -105,8 +105,24 @@ static double cell_terms_bound(const dc_grid* g, const dc_view& w, double D, con
   return best;
 }
 
+dc_status check_shape(const KernelShape& ks, std::string* err) {
+  if (ks.splat_kc < 0 || ks.splat_kc > 8) return fail(err, DC_EINVAL, "splat angles per workgroup must be 0..8");
+  if (ks.interp_tx != 32 && ks.interp_tx != 64) return fail(err, DC_EINVAL, "detector-BP tile width must be 32 or 64");
+  if (ks.interp_ty != 64) return fail(err, DC_EINVAL, "detector-BP tile height must be 64");
+  if (ks.interp_kc != 16 && ks.interp_kc != 32 && ks.interp_kc != 64)
+    return fail(err, DC_EINVAL, "detector-BP angles per chunk must be 16, 32 or 64");
+  if (ks.bp_bx != 16 || ks.bp_bz != 8 || (ks.bp_by != 16 && ks.bp_by != 32))
+    return fail(err, DC_EINVAL, "cone-BP block must be 16 x 16 x 8 or 16 x 32 x 8");
+  if (ks.fp_ti != 16 && ks.fp_ti != 20 && ks.fp_ti != 24) return fail(err, DC_EINVAL, "cone-FP tile width must be 16, 20 or 24");
+  return DC_OK;
+}
+
 dc_status plan_tables(const dc_grid* g, const dc_view* views, int n, const int* first, int n_samples,
                       const KernelShape& ks, HostPlan* p, std::string* err) {
+  {
+    const dc_status st = check_shape(ks, err);
+    if (st != DC_OK) return st;
+  }
   const int K = g->n_theta;
   p->ang.assign(3 * K, 0.0);
   p->trig.assign(2 * K, 0.f);
@@ -130,13 +146,21 @@ dc_status plan_tables(const dc_grid* g, const dc_view* views, int n, const int* 
   if (wl > kMaxInterpWindow)
     return fail(err, DC_ENOTSUP, "detector pitch too coarse for the s-bin width (ds << du): detector-BP window of " +
                                      std::to_string(wl) + " intervals (limit " + std::to_string(kMaxInterpWindow) + ")");
+  // the window rows of one angle chunk, 8 bytes per interval, plus the kernel's
+  // own per-angle tables (under 4 KiB), in one workgroup's LDS
+  if ((long long)ks.interp_kc * wl * 8 + 4096 > kLdsPerWorkgroup)
+    return fail(err, DC_ENOTSUP, "detector-BP window of " + std::to_string(wl) + " intervals x " +
+                                     std::to_string(ks.interp_kc) + " angles exceeds a workgroup's LDS");
 
   // Radon work list: runs of angles whose pixels spread fastest along rows
   // (|A| >= |B|, lanes walk i) or along columns (lanes walk j), cut into chunks.
   // LDS holds kc rows of (n_s + 1) 64-bit accumulators, at most 80 KiB so that two
   // workgroups share a CU's 160 KiB (1381 bins, a 976^2 detector: 7 angles, 15-17%
   // faster than the 5 a 64 KiB budget allows)
-  const int kc = std::max(1, std::min(8, 10240 / (g->n_s + 1)));
+  int kc = ks.splat_kc > 0 ? ks.splat_kc : std::max(1, std::min(8, 10240 / (g->n_s + 1)));
+  if ((long long)kc * (g->n_s + 1) * 8 + 1024 > kLdsPerWorkgroup)
+    return fail(err, DC_ENOTSUP, std::to_string(kc) + " sinogram rows of " + std::to_string(g->n_s) +
+                                     " bins per splat workgroup exceed its LDS");
   p->splat_kc = kc;
   // bound on pixels sharing one bin on one angle, and whether every pixel's
   // bin index stays in [-1, n_s - 1] (then the splat needs no range checks)

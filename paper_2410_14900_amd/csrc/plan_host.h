@@ -11,13 +11,27 @@
 
 namespace dc {
 
-// Work shapes of the kernels whose bounds the plan derives: the detector BP's
-// pixel tile and the cone BP's voxel block (edges and threads per workgroup).
+// Work shapes of the kernels (the plan's knobs), whose bounds the plan derives:
+//   splat_kc   angles per splat workgroup (sinogram rows held in LDS), 1..8; 0 picks
+//              the most that fit 80 KiB of LDS (two workgroups per CU);
+//   interp_tx  detector-BP pixel tile width, 32 or 64 (height interp_ty = 64);
+//   interp_kc  detector-BP angles per chunk, 16, 32 or 64;
+//   bp_by      cone-BP voxel block rows, 16 or 32 (block bp_bx x bp_by x bp_bz = 16 x . x 8);
+//   fp_ti      cone-FP detector tile width, 16, 20 or 24 (height 64).
+// The defaults are the values hand-tuned on the 256^3 / 512^2 training workload.
 struct KernelShape {
-  int interp_tx = 64, interp_ty = 64;
+  int splat_kc = 0;
+  int interp_tx = 64, interp_ty = 64, interp_kc = 32;
   int bp_bx = 16, bp_by = 32, bp_bz = 8;
+  int fp_ti = 20;
   int bp_threads() const { return bp_bx * bp_by; }
 };
+// Largest LDS one workgroup may hold on gfx950 (bytes), and the interp's largest angle chunk.
+static constexpr int kLdsPerWorkgroup = 160 * 1024;
+static constexpr int kInterpMaxKC = 64;
+
+// DC_OK if the shape is one the kernels are built for (DC_EINVAL otherwise, message in *err).
+dc_status check_shape(const KernelShape& ks, std::string* err);
 
 enum ConeForm : char { kConeGeneral = 0, kConeNewton = 1, kConeZinv = 2 };
 

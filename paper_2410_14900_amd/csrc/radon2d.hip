@@ -231,22 +231,21 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
 // wl/2 whose rounding (and that of A, B in float32) grows with the window: at
 // bins a fifth of the pixel pitch (wl = 450) it leaves 1.2e-5 against the
 // oracle, above the float32 bar.
-static constexpr int kTX = 64, kTY = 64, kKC = 32;
-static constexpr int kIPThreads = kTX * 8;   // 512: 8 row groups
+// Tile: TX x 64 pixels (TX = 32 or 64, the plan's knob; TX 8 threads); angles
+// per chunk kc <= kInterpMaxKC (knob, at run time).
+static constexpr int kTY = 64;
 static constexpr int kTPX = kTY / 8;   // pixels per thread (rows 8 apart)
 
-int interp_tile(int axis) { return axis == 0 ? kTX : kTY; }
-
-template <typename Tin, typename Tout, bool WCOS, bool LOCAL>
-__global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ rows, Tout* __restrict__ out, KGrid g,
-                                                const double* __restrict__ angd,
-                                                const float4* __restrict__ viewf, float scale, int v0, int nv,
-                                                int wl, int tiles_u, int n_tiles) {
+template <typename Tin, typename Tout, bool WCOS, bool LOCAL, int TX>
+__global__ __launch_bounds__(TX * 8) void k_interp(const Tin* __restrict__ rows, Tout* __restrict__ out, KGrid g,
+                                                   const double* __restrict__ angd,
+                                                   const float4* __restrict__ viewf, float scale, int v0, int nv,
+                                                   int wl, int kc, int tiles_u, int n_tiles) {
   extern __shared__ float2 win[];
-  __shared__ float4 sPar[kKC];   // A, B, t(tile origin) - w0 - 0.5 - wc, kk * wl + wc - bits(1.5 2^23) (int bits)
-  __shared__ int sW0[kKC];       // first bin of each angle's window
-  __shared__ double sParD[LOCAL ? kKC : 1][3];     // LOCAL: A, B, t(tile origin) - w0 in float64
-  __shared__ long long sStep8[LOCAL ? kKC : 1];    // LOCAL: 8 B in 32.32 fixed point
+  __shared__ float4 sPar[kInterpMaxKC];   // A, B, t(tile origin) - w0 - 0.5 - wc, kk * wl + wc - bits(1.5 2^23) (int bits)
+  __shared__ int sW0[kInterpMaxKC];       // first bin of each angle's window
+  __shared__ double sParD[LOCAL ? kInterpMaxKC : 1][3];     // LOCAL: A, B, t(tile origin) - w0 in float64
+  __shared__ long long sStep8[LOCAL ? kInterpMaxKC : 1];    // LOCAL: 8 B in 32.32 fixed point
   // XCD-aware order: all tiles of a view run on one XCD (its sinogram stays in one L2)
   const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
   const int vl = xcd + 8 * (kb / n_tiles);
@@ -254,21 +253,21 @@ __global__ __launch_bounds__(kIPThreads) void k_interp(const Tin* __restrict__ r
   const int v = v0 + vl;
   const int tile = kb % n_tiles;
   const int tu = tile % tiles_u, tv = tile / tiles_u;
-  const int i0 = tu * kTX, j0 = tv * kTY;
-  const int tx = threadIdx.x & (kTX - 1), ty = threadIdx.x / kTX;  // ty in [0, 8)
+  const int i0 = tu * TX, j0 = tv * kTY;
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;  // ty in [0, 8)
   const int ns = g.n_s;
   const Tin* rv = rows + (size_t)v * g.n_theta * ns;
   float acc[kTPX];
 #pragma unroll
   for (int h = 0; h < kTPX; ++h) acc[h] = 0.f;
-  for (int k0 = 0; k0 < g.n_theta; k0 += kKC) {
+  for (int k0 = 0; k0 < g.n_theta; k0 += kc) {
     // uniform: held in a scalar register, so the angle loop costs no vector instructions
-    const int kn = __builtin_amdgcn_readfirstlane(min(kKC, g.n_theta - k0));
+    const int kn = __builtin_amdgcn_readfirstlane(min(kc, g.n_theta - k0));
     if (threadIdx.x < kn) {
       const int k = k0 + threadIdx.x;
       const double A = angd[3 * k], B = angd[3 * k + 1], C = angd[3 * k + 2];
       const double t00 = C + i0 * A + j0 * B;
-      const double tmin = t00 + fmin(0.0, (kTX - 1) * A) + fmin(0.0, (kTY - 1) * B);
+      const double tmin = t00 + fmin(0.0, (TX - 1) * A) + fmin(0.0, (kTY - 1) * B);
       const int w0 = (int)floor(tmin) - 1;
       sW0[threadIdx.x] = w0;
       sPar[threadIdx.x] = make_float4((float)A, (float)B, (float)(t00 - w0 - 0.5 - (wl >> 1)),
@@ -411,17 +410,23 @@ hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos
 
 hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wcos, float scale, void* out,
                          dc_dtype t_out, int v0, int nv, hipStream_t s) {
-  const int tiles_u = (p.kg.nu + kTX - 1) / kTX, tiles_v = (p.kg.nv + kTY - 1) / kTY;
-  const size_t lds = (size_t)kKC * p.interp_wl * sizeof(float2);
+  const int TXr = p.shape.interp_tx, kc = p.shape.interp_kc;
+  const int tiles_u = (p.kg.nu + TXr - 1) / TXr, tiles_v = (p.kg.nv + kTY - 1) / kTY;
+  const size_t lds = (size_t)kc * p.interp_wl * sizeof(float2);
   const int n_tiles = tiles_u * tiles_v;
   dim3 grid(8 * ((nv + 7) / 8) * n_tiles);
   return by_dtype(t_in, [&](auto tin) {
     using Tin = decltype(tin);
     return by_dtype(t_out, [&](auto tout) {
       using Tout = decltype(tout);
-#define DC_INTERP(W, L)                                                                                          \
-  hipLaunchKernelGGL((k_interp<Tin, Tout, W, L>), grid, dim3(kIPThreads), lds, s, (const Tin*)rows, (Tout*)out, \
-                     p.kg, p.d_ang, (const float4*)p.d_view, scale, v0, nv, p.interp_wl, tiles_u, n_tiles)
+#define DC_INTERP1(W, L, TX)                                                                                     \
+  hipLaunchKernelGGL((k_interp<Tin, Tout, W, L, TX>), grid, dim3(TX * 8), lds, s, (const Tin*)rows, (Tout*)out,  \
+                     p.kg, p.d_ang, (const float4*)p.d_view, scale, v0, nv, p.interp_wl, kc, tiles_u, n_tiles)
+#define DC_INTERP(W, L)                      \
+  do {                                       \
+    if (TXr == 32) DC_INTERP1(W, L, 32);     \
+    else DC_INTERP1(W, L, 64);               \
+  } while (0)
       const bool local = p.interp_wl > kInterpLocalAbove;
       if (wcos) {
         if (local) DC_INTERP(true, true); else DC_INTERP(true, false);
@@ -429,6 +434,7 @@ hipError_t launch_interp(const Plan& p, const void* rows, dc_dtype t_in, bool wc
         if (local) DC_INTERP(false, true); else DC_INTERP(false, false);
       }
 #undef DC_INTERP
+#undef DC_INTERP1
       return hipGetLastError();
     });
   });

@@ -88,6 +88,38 @@ class Plan:
         first = np.concatenate([[0], np.cumsum([len(p) for p in parts])])
         return cls(grid, np.concatenate(parts), first_view=first)
 
+    KNOB_NAMES = ("splat_angles", "interp_tile_u", "interp_angles", "bp_block_y", "fp_tile_u")
+
+    def knobs(self):
+        """The kernels' work shapes (dc_plan_get_knobs) as a dict."""
+        k = _lib.DcKnobs()
+        check(_lib.lib().dc_plan_get_knobs(self.handle, ctypes.byref(k)), "dc_plan_get_knobs")
+        return {n: getattr(k, n) for n in self.KNOB_NAMES}
+
+    def set_knobs(self, **values):
+        """Sets some knobs (dc_plan_set_knobs); the others keep their values."""
+        cur = self.knobs()
+        unknown = set(values) - set(cur)
+        if unknown:
+            raise ValueError("unknown knobs: %s" % sorted(unknown))
+        cur.update(values)
+        k = _lib.DcKnobs(**{n: int(cur[n]) for n in self.KNOB_NAMES})
+        check(_lib.lib().dc_plan_set_knobs(self.handle, ctypes.byref(k)), "dc_plan_set_knobs")
+        return self.knobs()
+
+    def autotune(self, stream=None):
+        """Times the knob candidates on this plan's geometry and keeps the fastest
+        (dc_plan_autotune; DCFBP_KNOBS and DCFBP_TUNE_CACHE apply).  Returns
+        {"knobs": ..., "ms": {stage: ms}, "source": "timed" | "cache" | "environment"}."""
+        k = _lib.DcKnobs()
+        ms = (ctypes.c_double * 4)()
+        src = ctypes.c_int32()
+        check(_lib.lib().dc_plan_autotune(self.handle, 0, _stream(stream), ctypes.byref(k), ms, ctypes.byref(src)),
+              "dc_plan_autotune")
+        return {"knobs": {n: getattr(k, n) for n in self.KNOB_NAMES},
+                "ms": dict(zip(("weight_radon", "detector_bp", "cone_bp", "cone_bp_adjoint"), list(ms))),
+                "source": ("timed", "cache", "environment")[src.value]}
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.lib().dc_plan_destroy(self.handle)
