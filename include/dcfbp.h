@@ -42,7 +42,8 @@
  * tables (immutable after creation), a scratch word per view and per sample that
  * dc_weight_radon, dc_detector_bp_adjoint and dc_cone_bp_adjoint use for their
  * fixed-point scales, and one volume-sized float32 buffer per sample into which
- * dc_cone_bp_adjoint writes the ReLU-masked gradient; stage calls on one plan
+ * dc_cone_bp_adjoint rewrites the (ReLU-masked) gradient in z-bricks of 16
+ * voxels (nz rounded up to a multiple of 16); stage calls on one plan
  * must therefore be ordered on one stream (use one plan per concurrent stream).  Plans must be created before any stream
  * capture that uses them; stage calls enqueue kernels only (no memset, no
  * allocation), so they can be captured into a graph.
@@ -145,8 +146,10 @@ dc_status dc_plan_get_knobs(dc_plan plan, dc_knobs* out);
 dc_status dc_plan_set_knobs(dc_plan plan, const dc_knobs* knobs);
 /* The autotuner: times every candidate value of each knob on the plan's own
  * geometry and sets the fastest.  Each stage is timed (on `stream`, one warm-up and
- * three timed runs, the fastest kept) over up to four runs of 8 consecutive views
- * spread over the plan, on seeded synthetic inputs in temporary device buffers
+ * three timed runs, the fastest kept) over up to four runs of 32 consecutive views
+ * spread over the plan; the knobs held so far are timed first and a candidate
+ * replaces them only if it is more than 2% faster.  Inputs are seeded synthetic
+ * ones in temporary device buffers
  * allocated and freed inside the call: dc_weight_radon for splat_angles,
  * dc_detector_bp for interp_tile_u x interp_angles, dc_cone_bp for bp_block_y and
  * dc_cone_bp_adjoint (with a ReLU mask) for fp_tile_u.

@@ -71,7 +71,8 @@ static dc_status build_plan(const dc_grid* g, const dc_view* views, int32_t n, c
   if (st != DC_OK) return st;
   hipError_t e;
   if ((e = hipMalloc((void**)&p->d_scratch, (n + n_samples) * sizeof(unsigned))) != hipSuccess ||
-      (e = hipMalloc((void**)&p->d_masked, (size_t)n_samples * g->nx * g->ny * g->nz * sizeof(float))) !=
+      (e = hipMalloc((void**)&p->d_masked, (size_t)n_samples * g->nx * g->ny *
+                                               ((g->nz + kConeBrick - 1) / kConeBrick * kConeBrick) * sizeof(float))) !=
           hipSuccess)
     return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP, std::string("plan scratch: ") + hipGetErrorString(e));
   return DC_OK;

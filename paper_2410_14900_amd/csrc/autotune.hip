@@ -130,9 +130,13 @@ struct Sample {
   int last = 0;                              // one past the highest view touched
 };
 
+// Up to four evenly spaced ranges of 32 consecutive views: launches of that
+// size fill the GPU as the full view range does (narrower launches favour
+// smaller workgroups that lose at full size), and spread ranges see views of
+// every direction.
 static Sample sample_views(int V) {
   Sample s;
-  const int L = std::min(8, V);
+  const int L = std::min(32, V);
   const int R = std::min(4, (V + L - 1) / L);
   for (int i = 0; i < R; ++i) {
     const int v0 = R > 1 ? (int)((long long)i * (V - L) / (R - 1)) : 0;
@@ -173,19 +177,23 @@ struct Buffers {
   }
 };
 
-// One stage's candidate shapes: each is applied to the plan, timed, and the
-// fastest returned in *best (with its time).  Shapes the geometry rejects (LDS)
-// are skipped.
+// One stage's candidate shapes: the incumbent (the plan's shape so far) is timed
+// first, then each candidate is applied to the plan and timed; a candidate
+// replaces the best so far only if it is faster by more than 2% (timing noise
+// between launches is about 1%), and the best is returned in *best (with its
+// time).  Shapes the geometry rejects (LDS) are skipped.
 template <typename Run>
-static hipError_t tune_stage(Plan* p, hipStream_t s, const std::vector<KernelShape>& cands, Run&& run,
-                             KernelShape* best, double* best_ms) {
+static hipError_t tune_stage(Plan* p, hipStream_t s, const KernelShape& incumbent,
+                             const std::vector<KernelShape>& cands, Run&& run, KernelShape* best, double* best_ms) {
   *best_ms = 1e300;
-  for (const KernelShape& ks : cands) {
+  std::vector<KernelShape> order{incumbent};
+  order.insert(order.end(), cands.begin(), cands.end());
+  for (const KernelShape& ks : order) {
     if (set_shape(p, ks) != DC_OK) continue;
     double ms = 0.0;
     const hipError_t e = time_it(s, run, &ms);
     if (e != hipSuccess) return e;
-    if (ms < *best_ms) {
+    if (ms < (*best_ms < 1e300 ? 0.98 * *best_ms : *best_ms)) {
       *best_ms = ms;
       *best = ks;
     }
@@ -271,7 +279,7 @@ dc_status autotune(Plan* p, hipStream_t s, dc_knobs* chosen, double* ms_out, int
       k.splat_kc = kc;
       c.push_back(k);
     }
-    e = tune_stage(p, s, c, over_ranges([&](int v0, int nv) {
+    e = tune_stage(p, s, cur, c, over_ranges([&](int v0, int nv) {
                      return launch_splat(*p, b.img, DC_F32, true, scale_r, b.sino, DC_F32, v0, nv, s);
                    }),
                    &best, &best_ms);
@@ -290,7 +298,7 @@ dc_status autotune(Plan* p, hipStream_t s, dc_knobs* chosen, double* ms_out, int
         k.interp_kc = kc;
         c.push_back(k);
       }
-    e = tune_stage(p, s, c, over_ranges([&](int v0, int nv) {
+    e = tune_stage(p, s, cur, c, over_ranges([&](int v0, int nv) {
                      return launch_interp(*p, b.sino, DC_F32, false, scale_b, b.img2, DC_F32, v0, nv, s);
                    }),
                    &best, &best_ms);
@@ -308,7 +316,7 @@ dc_status autotune(Plan* p, hipStream_t s, dc_knobs* chosen, double* ms_out, int
       k.bp_by = by;
       c.push_back(k);
     }
-    e = tune_stage(p, s, c, over_ranges([&](int v0, int nv) {
+    e = tune_stage(p, s, cur, c, over_ranges([&](int v0, int nv) {
                      return launch_cone_bp(*p, b.img, DC_F32, b.vol2, 0, 1, v0, nv, s);
                    }),
                    &best, &best_ms);
@@ -325,7 +333,7 @@ dc_status autotune(Plan* p, hipStream_t s, dc_knobs* chosen, double* ms_out, int
       k.fp_ti = ti;
       c.push_back(k);
     }
-    e = tune_stage(p, s, c, over_ranges([&](int v0, int nv) {
+    e = tune_stage(p, s, cur, c, over_ranges([&](int v0, int nv) {
                      return launch_cone_fp(*p, b.vol, b.mask, b.img2, DC_F32, v0, nv, s);
                    }),
                    &best, &best_ms);

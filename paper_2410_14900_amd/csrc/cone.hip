@@ -29,6 +29,14 @@ static constexpr int kBX = 16, kZC = 8;
 static constexpr float kRoundMagic = 12582912.0f;         // 1.5 * 2^23
 static constexpr unsigned kRoundMagicBits = 0x4B400000u;  // its bit pattern
 
+// Two terms a and b rounded with the 1.5 * 2^23 trick (|a|, |b| < 2^22), as the
+// 64-bit word b 2^32 + a: subtracting both biases at once lets the borrow carry
+// the sign of a into the high word.
+__device__ __forceinline__ unsigned long long pack_terms(float a_biased, float b_biased) {
+  constexpr unsigned long long kBias = ((unsigned long long)kRoundMagicBits << 32) | kRoundMagicBits;
+  return ((((unsigned long long)__float_as_uint(b_biased)) << 32) | __float_as_uint(a_biased)) - kBias;
+}
+
 struct ColumnMap {
   float den, dden;   // den = U/D at the segment start and its z step
   float lu, ldu;     // num_u - iu0 den and its z step
@@ -80,6 +88,47 @@ __device__ __forceinline__ ColumnMapZ column_map_z(const double* __restrict__ P,
   c.r2 = rden * rden;
   c.w0m = (float)fma(-(double)jv0, den, nv) * rden - 0.5f;
   c.dw = (float)P[10] * rden;
+  return c;
+}
+
+// Column set-up of the cone adjoint's general forms.  The numerators are taken
+// about iu0 + 1/2 and jv0 + 1/2 (any integers within a pixel of the projection:
+// the hardware reciprocal serves), so n rr = u - iu0 - 1/2 and likewise v, and
+// every coordinate is scaled by sf = 1/sqrt(S), so rr^2 = S (D/U)^2 carries the
+// fixed-point quantum.  den and the numerators at the segment start are formed in
+// float64 (where they cancel).  With FLOAT_STEPS (den changes by at most 2.5e-4
+// of itself per voxel step) their z-steps are formed in float from the view's
+// scaled steps zd, zu, zv (dden, dnum_u, dnum_v): the product au zd is then at
+// most 2.5e-4 au den, so the step's error stays near one rounding of it;
+// otherwise they are formed in float64.
+struct ColumnMapF {
+  float den, lu, lv;   // at the first voxel of the segment
+  float ldu, ldv;      // z-steps of the numerators
+  int iu0, jv0;
+};
+
+template <bool FLOAT_STEPS>
+__device__ __forceinline__ ColumnMapF column_map_fp(const double* __restrict__ P, int ix, int iy, int iz0, float sf,
+                                                    float zd, float zu, float zv) {
+  const double den = fma((double)ix, P[0], fma((double)iy, P[1], fma((double)iz0, P[2], P[3])));
+  const double nu = fma((double)ix, P[4], fma((double)iy, P[5], fma((double)iz0, P[6], P[7])));
+  const double nv = fma((double)ix, P[8], fma((double)iy, P[9], fma((double)iz0, P[10], P[11])));
+  const float rden = __builtin_amdgcn_rcpf((float)den);
+  const float yu = fmaf((float)nu, rden, kRoundMagic), yv = fmaf((float)nv, rden, kRoundMagic);
+  const float au = (yu - kRoundMagic) + 0.5f, av = (yv - kRoundMagic) + 0.5f;   // exact
+  ColumnMapF c;
+  c.iu0 = (int)(__float_as_uint(yu) - kRoundMagicBits);
+  c.jv0 = (int)(__float_as_uint(yv) - kRoundMagicBits);
+  c.den = (float)den * sf;
+  c.lu = (float)fma(-(double)au, den, nu) * sf;
+  c.lv = (float)fma(-(double)av, den, nv) * sf;
+  if (FLOAT_STEPS) {
+    c.ldu = fmaf(-au, zd, zu);
+    c.ldv = fmaf(-av, zd, zv);
+  } else {
+    c.ldu = (float)fma(-(double)au, P[2], P[6]) * sf;
+    c.ldv = (float)fma(-(double)av, P[2], P[10]) * sf;
+  }
   return c;
 }
 
@@ -346,18 +395,22 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
 // item, walked in z like the backprojection.
 //
 // A voxel with fractional projection (ib + fu, jb + fv) and weight g adds
-// g(1-fu)(1-fv), g fu(1-fv), g(1-fu)fv, g fu fv to its four taps.  The four sums
-// A = sum g, B = sum g fu, C = sum g fv, E = sum g fu fv are kept at index
-// (ib, jb) as fixed-point integers packed two per 64-bit word and added with
-// LDS integer atomics; the tile is decoded at the end as
-//   out(i,j) = A - B - C + E |(i,j) + (B - E)|(i-1,j) + (C - E)|(i,j-1) + E|(i-1,j-1).
+// g(1-fu)(1-fv), g fu(1-fv), g(1-fu)fv, g fu fv to its four taps.  With the
+// centred fractions a = fu - 1/2 and b = fv - 1/2 (what the rounding leaves,
+// so no second subtraction) the four sums A = sum g, B = sum g a, C = sum g b,
+// E = sum g a b are kept at index (ib, jb) as fixed-point integers packed two
+// per 64-bit word and added with LDS integer atomics; each tap weight is
+// (1/2 -+ a)(1/2 -+ b), so the tile is decoded at the end as
+//   out(i,j) = A/4 [c + l + d + e] + B/2 [-c + l - d + e] + C/2 [-c - l + d + e]
+//              + E [c - l - d + e]
+// over the cell itself (c) and its left (l), lower (d) and lower-left (e) neighbours.
 // Integer sums make the result bit-reproducible.  The fixed-point quantum comes
 // from max |Gf| (a reduction kernel into the plan's scratch, which also applies
 // the ReLU mask once into the plan's volume buffer) and the per-view bound on
 // (D/U)^2, sized so no index's sums leave 32 bits.  Only z-layers whose
 // box can reach the tile's window are scanned.
 // Tile: TI x kFTJ pixels, TI = 16, 20 or 24 (the plan's knob).
-static constexpr int kFTJ = 64, kFZS = 16, kFROWS = 512;
+static constexpr int kFTJ = 64, kFZS = kConeBrick, kFROWS = 512;
 static constexpr int kFH = kFTJ + 1;
 
 __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
@@ -376,26 +429,40 @@ __device__ __forceinline__ int block_exclusive_scan_256(int v, int* tmp) {
   return incl - v;
 }
 
-// max |Gf * mask| over the volume, as float bits; with a mask the masked
-// gradient is also written out (once) for the gather to read
-__global__ __launch_bounds__(256) void k_vol_absmax(const float* __restrict__ Gf, const float* __restrict__ f_relu,
-                                                    size_t n, unsigned* __restrict__ out,
-                                                    float* __restrict__ masked) {
+// The gradient (times the ReLU mask when there is one) rewritten in z-bricks,
+// [ceil(nz/16)][ny][nx][16] per sample, with zeros past the last slice, so a
+// 16-voxel z-segment is 64 contiguous bytes; and max |Gf * mask| per sample, as
+// float bits.  One thread per brick: the reads of a slice are coalesced along x,
+// and the 64-byte brick is written at once.
+__global__ __launch_bounds__(256) void k_vol_brick(const float* __restrict__ Gf, const float* __restrict__ f_relu,
+                                                   int nx, int ny, int nz, unsigned* __restrict__ out,
+                                                   float* __restrict__ bricks) {
   __shared__ float red[256];
-  // grid y = sample: one volume of n voxels each
-  const size_t base = (size_t)blockIdx.y * n;
-  Gf += base;
-  if (f_relu) f_relu += base;
-  masked += base;
+  // grid y = sample: one volume of nx ny nz voxels each
+  const size_t plane = (size_t)nx * ny, n = plane * nz;
+  const int nzs = (nz + kFZS - 1) / kFZS;
+  const size_t ncol = plane * nzs;
+  Gf += (size_t)blockIdx.y * n;
+  if (f_relu) f_relu += (size_t)blockIdx.y * n;
+  bricks += (size_t)blockIdx.y * ncol * kFZS;
   out += blockIdx.y;
   float mx = 0.f;
-  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
-    float x = Gf[q];
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < ncol; q += (size_t)gridDim.x * blockDim.x) {
+    const size_t zs = q / plane, xy = q - zs * plane;
+    const int nzv = min(kFZS, nz - (int)zs * kFZS);
+    const size_t src = zs * kFZS * plane + xy;
+    float v[kFZS];
+#pragma unroll
+    for (int z = 0; z < kFZS; ++z) v[z] = z < nzv ? Gf[src + z * plane] : 0.f;
     if (f_relu) {
-      x = f_relu[q] > 0.f ? x : 0.f;
-      masked[q] = x;
+#pragma unroll
+      for (int z = 0; z < kFZS; ++z) v[z] = z < nzv && f_relu[src + z * plane] > 0.f ? v[z] : 0.f;
     }
-    mx = fmaxf(mx, fabsf(x));
+#pragma unroll
+    for (int z = 0; z < kFZS; ++z) mx = fmaxf(mx, fabsf(v[z]));
+    float4* dst = reinterpret_cast<float4*>(bricks + q * kFZS);
+#pragma unroll
+    for (int k = 0; k < kFZS / 4; ++k) dst[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
   }
   red[threadIdx.x] = mx;
   __syncthreads();
@@ -419,13 +486,14 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
 }
 
 
-// CLAMP: the volume is so wide and shallow that the byte offset of a z-segment
-// running past its last slice could pass 2^32; indices are then clamped into
-// the volume (and their values dropped) instead of left to the buffer's range check.
+// Gf: the z-bricked (masked) gradient written by k_vol_brick.
 // FORM (ConeForm) as in the backprojection; with kConeZinv each (segment, view)
 // has one u, one tap column and one weight, and a segment whose column misses
-// the tile is skipped whole.
-template <typename Tout, bool CLAMP, int FORM, int TI>
+// the tile is skipped whole.  With kConeNewton (den changes by at most 2.5e-4 of
+// itself per voxel step) 1/den along the segment is its quadratic Taylor
+// polynomial about the first voxel: the remainder is below (15 x 2.5e-4)^3 =
+// 5.3e-8 of it, float rounding, and every voxel's reciprocal is independent.
+template <typename Tout, int FORM, int TI>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
                                                  const double* __restrict__ proj, const float* __restrict__ rmax2,
                                                  int v0, int nv, int tiles_u, int n_tiles, float qmax,
@@ -461,11 +529,8 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
     grp -= ng;
   }
   if (nvw <= 0) return;
-  Gf += (size_t)smp * g.nx * g.ny * g.nz;
-  // reads go through a buffer resource spanning this sample's volume: offsets past
-  // its end return 0 (the range check), so segments need no clamping
-  const __amdgpu_buffer_rsrc_t vol =
-      __builtin_amdgcn_make_buffer_rsrc((void*)Gf, (short)0, g.nx * g.ny * g.nz * 4, kBufferWord3);
+  const int nzs = (g.nz + kFZS - 1) / kFZS;
+  Gf += (size_t)smp * g.nx * g.ny * nzs * kFZS;
   const int ti = tile % tiles_u, tj = tile / tiles_u;
   const int i0 = ti * kFTI, i1 = min(g.nu, i0 + kFTI);
   const int j0 = tj * kFTJ, j1 = min(g.nv, j0 + kFTJ);
@@ -489,7 +554,6 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   }
   __syncthreads();
   // z-layers (16 slices each) whose box can reach the window of any of the views
-  const int nzs = (g.nz + kFZS - 1) / kFZS;
   for (int zs = threadIdx.x; zs < nzs; zs += blockDim.x) {
     const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
     bool any = false;
@@ -515,13 +579,20 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   }
   __syncthreads();
   const int nrows = sNL * g.ny;
-  const int plane = g.nx * g.ny;   // volumes are below 2^31 voxels (checked by the plan)
   const float gabs = __uint_as_float(gmax_bits[smp]);
-  float S[kFV];
+  // per view: the quantum S, 1/sqrt(S) (the general forms scale their
+  // coordinates by it) and the scaled z-steps of den, num_u and num_v
+  float S[kFV], sinv[kFV], zstep_d[kFV], zstep_u[kFV], zstep_v[kFV];
 #pragma unroll
   for (int w = 0; w < kFV; ++w) {
     const float gmax = w < nvw ? gabs * rmax2[va + w] : 0.f;
     S[w] = gmax > 0.f ? qmax / gmax : 0.f;
+    const double si = S[w] > 0.f ? 1.0 / sqrt((double)S[w]) : 1.0;   // S = 0: every term is zero anyway
+    const double* P = proj + 12 * (va + (w < nvw ? w : 0));
+    sinv[w] = (float)si;
+    zstep_d[w] = (float)(P[2] * si);
+    zstep_u[w] = (float)(P[6] * si);
+    zstep_v[w] = (float)(P[10] * si);
   }
   for (int r0 = 0; r0 < nrows; r0 += kFROWS) {
     if (threadIdx.x == 0) sCount = 0;
@@ -601,36 +672,29 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       const int ix = sXlo[lo] + (q - sPre[lo]);
       const int zs = sLay[lo];
       const int iz0 = zs * kFZS;
-      // Issue all of the segment's loads before using any of them, so their
-      // latencies overlap instead of serialising.
-      const int off = iz0 * plane + iy * g.nx + ix;
+      // the segment's brick: four 16-byte loads from one address (slices past the
+      // last one hold zeros); column indices stay below 2^29 (the plan bounds the
+      // volume), the byte offset is formed in 64 bits
+      const unsigned col = (unsigned)(zs * g.ny + iy) * (unsigned)g.nx + (unsigned)ix;
+      const float4* brick = reinterpret_cast<const float4*>(Gf) + (size_t)col * (kFZS / 4);
       float gv[kFZS];
-      if (CLAMP) {
-        const int nzv = min(kFZS, g.nz - iz0);
 #pragma unroll
-        for (int z = 0; z < kFZS; ++z) gv[z] = Gf[off + min(z, nzv - 1) * plane];
-#pragma unroll
-        for (int z = 0; z < kFZS; ++z) gv[z] = z < nzv ? gv[z] : 0.f;
-      } else {
-        // slices past the last one lie past the end of the volume and read 0
-        // byte offsets advanced by one add per slice (the slice step is uniform)
-        unsigned a = 4u * (unsigned)off;
-        const unsigned step = 4u * (unsigned)plane;
-#pragma unroll
-        for (int z = 0; z < kFZS; ++z) {
-          gv[z] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(vol, (int)a, 0, 0));
-          a += step;
-        }
+      for (int k = 0; k < kFZS / 4; ++k) {
+        const float4 q4 = brick[k];
+        gv[4 * k] = q4.x;
+        gv[4 * k + 1] = q4.y;
+        gv[4 * k + 2] = q4.z;
+        gv[4 * k + 3] = q4.w;
       }
       for (int w = 0; w < nvw; ++w) {
-        const float Sw = pick(S, w);
         unsigned long long* ab = sAB[w];
         unsigned long long* ce = sCE[w];
         if constexpr (FORM == kConeZinv) {
           const ColumnMapZ c = column_map_z(proj + 12 * (va + w), ix, iy, iz0);
           const int li = c.i - (i0 - 1);
           if ((unsigned)li > (unsigned)(i1 - i0)) continue;
-          const float K = c.r2 * Sw;   // (D/U)^2 S: every term stays below 2^21 (rmax2 carries a 1e-6 margin)
+          const float K = c.r2 * pick(S, w);   // (D/U)^2 S: every term stays below 2^21 (rmax2 carries a 1e-6 margin)
+          const float fuc = c.fu - 0.5f;   // centred fraction, in [-1/2, 1/2]
           const unsigned jbias = kRoundMagicBits - (unsigned)(c.jv0 - (j0 - 1));
 #pragma unroll
           for (int z = 0; z < kFZS; ++z) {
@@ -639,58 +703,51 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
             const int lj = (int)(__float_as_uint(yw) - jbias);
             const float x = gv[z];
             if (((unsigned)lj <= (unsigned)(j1 - j0)) & (x != 0.f)) {   // one branch, not two
-              const float fv = (wm - (yw - kRoundMagic)) + 0.5f;
+              const float fvc = wm - (yw - kRoundMagic);   // centred fraction of v
               const float gs = x * K;
-              const float gu = gs * c.fu;
-              const int qa = (int)(__float_as_uint(gs + kRoundMagic) - kRoundMagicBits);
-              const int qc = (int)(__float_as_uint(fmaf(gs, fv, kRoundMagic)) - kRoundMagicBits);
-              const unsigned hb =
-                  __float_as_uint(fmaf(gs, c.fu, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qa >> 31));
-              const unsigned he =
-                  __float_as_uint(fmaf(gu, fv, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qc >> 31));
+              const float gu = gs * fuc;
               const unsigned cell = __umul24((unsigned)lj, (unsigned)kFW) + li;   // lj < 2^24: 24-bit multiply
-              atomicAdd(ab + cell, ((unsigned long long)hb << 32) | (unsigned)qa);
-              atomicAdd(ce + cell, ((unsigned long long)he << 32) | (unsigned)qc);
+              atomicAdd(ab + cell, pack_terms(gs + kRoundMagic, fmaf(gs, fuc, kRoundMagic)));
+              atomicAdd(ce + cell, pack_terms(fmaf(gs, fvc, kRoundMagic), fmaf(gu, fvc, kRoundMagic)));
             }
           }
           continue;
         }
-        const ColumnMap c = column_map(proj + 12 * (va + w), ix, iy, iz0);
-        float rr = __builtin_amdgcn_rcpf(c.den);   // kConeNewton: Newton steps along z, as in the backprojection
+        const float zd = pick(zstep_d, w);
+        const ColumnMapF c = column_map_fp<FORM == kConeNewton>(proj + 12 * (va + w), ix, iy, iz0, pick(sinv, w), zd,
+                                                                 pick(zstep_u, w), pick(zstep_v, w));
+        float rr0 = __builtin_amdgcn_rcpf(c.den);
+        rr0 = fmaf(rr0, fmaf(-c.den, rr0, 1.0f), rr0);   // one Newton step: a correctly rounded start
+        const float r1 = -rr0 * rr0 * zd, r2 = -r1 * rr0 * zd;   // 1/den = rr0 + r1 z + r2 z^2
 #pragma unroll
         for (int z = 0; z < kFZS; ++z) {
-          if (z > 0) {
-            const float den = fmaf((float)z, c.dden, c.den);
-            rr = FORM == kConeNewton ? fmaf(rr, fmaf(-den, rr, 1.0f), rr) : __builtin_amdgcn_rcpf(den);
-          }
-          const float u = fmaf((float)z, c.ldu, c.lu) * rr;
-          const float wv = fmaf((float)z, c.ldv, c.lv) * rr;
-          // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer may give
-          // the cell below with fraction 1: the same taps, and range checks as usual)
-          const float yu = (u - 0.5f) + kRoundMagic, yw = (wv - 0.5f) + kRoundMagic;
-          const float fu0 = yu - kRoundMagic, fw0 = yw - kRoundMagic;
+          const float rr = z == 0 ? rr0
+                           : FORM == kConeNewton ? fmaf((float)z, r1, fmaf((float)(z * z), r2, rr0))
+                                                 : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
+          // nu rr = u - iu0 - 1/2 (and likewise v): one fused rounding with the
+          // 1.5 * 2^23 trick gives the cell floor(u) (an exact integer u may give the
+          // cell below with fraction 1: the same taps, and range checks as usual),
+          // and a second fused form the centred fraction fu - 1/2 in [-1/2, 1/2]
+          const float nu = z == 0 ? c.lu : fmaf((float)z, c.ldu, c.lu);
+          const float nv = z == 0 ? c.lv : fmaf((float)z, c.ldv, c.lv);
+          const float yu = fmaf(nu, rr, kRoundMagic), yw = fmaf(nv, rr, kRoundMagic);
           const int li = c.iu0 + (int)(__float_as_uint(yu) - kRoundMagicBits) - (i0 - 1);
           const int lj = c.jv0 + (int)(__float_as_uint(yw) - kRoundMagicBits) - (j0 - 1);
           const float x = gv[z];
-          // bitwise rather than short-circuit: one branch per voxel
+          // bitwise rather than short-circuit: one branch per voxel.  Zero voxels (the
+          // ReLU mask zeroes about half of a reconstruction) skip their two atomics.
           if (((unsigned)li <= (unsigned)(i1 - i0)) & ((unsigned)lj <= (unsigned)(j1 - j0)) & (x != 0.f)) {
-            const float fu = u - fu0, fv = wv - fw0;
-            const float gs = x * rr * rr * Sw;
+            const float fu = fmaf(nu, rr, kRoundMagic - yu), fv = fmaf(nv, rr, kRoundMagic - yw);
+            const float xr = x * rr;
+            const float gs = xr * rr;
             const float gu = gs * fu;
             // Integer rounding without conversion instructions: adding 1.5 * 2^23
             // leaves round-to-nearest-even(v) in the low mantissa bits for
             // |v| < 2^22 (every term is below 2^21), and the fused forms round
-            // the products gs fu, gs fv, gu fv once.  The high words take the
-            // sign extension of the low ones through their bias.
-            const int qa = (int)(__float_as_uint(gs + kRoundMagic) - kRoundMagicBits);
-            const int qc = (int)(__float_as_uint(fmaf(gs, fv, kRoundMagic)) - kRoundMagicBits);
-            const unsigned hb = __float_as_uint(fmaf(gs, fu, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qa >> 31));
-            const unsigned he = __float_as_uint(fmaf(gu, fv, kRoundMagic)) - (kRoundMagicBits - (unsigned)(qc >> 31));
-            const unsigned long long w1 = ((unsigned long long)hb << 32) | (unsigned)qa;
-            const unsigned long long w2 = ((unsigned long long)he << 32) | (unsigned)qc;
+            // the products gs fu, gs fv, gu fv once.
             const unsigned cell = __umul24((unsigned)lj, (unsigned)kFW) + li;   // lj < 2^24: 24-bit multiply
-            atomicAdd(ab + cell, w1);
-            atomicAdd(ce + cell, w2);
+            atomicAdd(ab + cell, pack_terms(fmaf(xr, rr, kRoundMagic), fmaf(gs, fu, kRoundMagic)));
+            atomicAdd(ce + cell, pack_terms(fmaf(gs, fv, kRoundMagic), fmaf(gu, fv, kRoundMagic)));
           }
         }
       }
@@ -711,15 +768,24 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       const int i = i0 + di, j = j0 + dj;
       if (i >= i1 || j >= j1) continue;
       const int li = di + 1, lj = dj + 1;
-      const unsigned long long ab = AB[lj * kFW + li], ce = CE[lj * kFW + li];
-      const unsigned long long abl = AB[lj * kFW + li - 1], cel = CE[lj * kFW + li - 1];
-      const unsigned long long ced = CE[(lj - 1) * kFW + li], celd = CE[(lj - 1) * kFW + li - 1];
-      const long long A = lo32(ab), B = hi32(ab, A), C = lo32(ce), E = hi32(ce, C);
-      const long long Bl = hi32(abl, lo32(abl)), Cl = lo32(cel), El = hi32(cel, Cl);
-      const long long Cd = lo32(ced), Ed = hi32(ced, Cd);
-      const long long Eld = hi32(celd, lo32(celd));
-      const long long val = A - B - C + E + (Bl - El) + (Cd - Ed) + Eld;
-      o[j * g.nu + i] = from_f32<Tout>((float)((double)val * invS));
+      // the sums of the cell itself (c), its left (l), lower (d) and lower-left (e)
+      // neighbours, with centred fractions a = fu - 1/2, b = fv - 1/2:
+      // (1 - fu)(1 - fv) = (1/2 - a)(1/2 - b), fu (1 - fv) = (1/2 + a)(1/2 - b), ...
+      long long A[4], B[4], C[4], E[4];
+      const int cells[4] = {lj * kFW + li, lj * kFW + li - 1, (lj - 1) * kFW + li, (lj - 1) * kFW + li - 1};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const unsigned long long ab = AB[cells[c]], ce = CE[cells[c]];
+        A[c] = lo32(ab);
+        B[c] = hi32(ab, A[c]);
+        C[c] = lo32(ce);
+        E[c] = hi32(ce, C[c]);
+      }
+      // exact in float64: integers below 2^40 in halves and quarters
+      const double val = 0.25 * (double)(A[0] + A[1] + A[2] + A[3]) +
+                         0.5 * (double)(-B[0] + B[1] - B[2] + B[3]) +
+                         0.5 * (double)(-C[0] - C[1] + C[2] + C[3]) + (double)(E[0] - E[1] - E[2] + E[3]);
+      o[j * g.nu + i] = from_f32<Tout>((float)(val * invS));
     }
   }
 }
@@ -788,16 +854,16 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
   hipError_t e = launch_zero_u32(gmax + s_lo, n_smp, s);
   if (e != hipSuccess) return e;
   const size_t n = (size_t)p.kg.nx * p.kg.ny * p.kg.nz;
-  const int blocks = (int)std::min<size_t>(2048, (n + 255) / 256);
-  hipLaunchKernelGGL(k_vol_absmax, dim3(blocks, n_smp), dim3(256), 0, s, Gf + s_lo * n,
-                     f_relu ? f_relu + s_lo * n : nullptr, n, gmax + s_lo, p.d_masked + s_lo * n);
+  const size_t ncol = (size_t)p.kg.nx * p.kg.ny * ((p.kg.nz + kFZS - 1) / kFZS);
+  const int blocks = (int)std::min<size_t>(4096, (ncol + 255) / 256);
+  hipLaunchKernelGGL(k_vol_brick, dim3(blocks, n_smp), dim3(256), 0, s, Gf + s_lo * n,
+                     f_relu ? f_relu + s_lo * n : nullptr, p.kg.nx, p.kg.ny, p.kg.nz, gmax + s_lo,
+                     p.d_masked + s_lo * ncol * kFZS);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int n_tiles = tiles_u * tiles_v;
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
-    const float* src = f_relu ? p.d_masked : Gf;
-    // the largest byte offset a segment forms: (nz rounded up to a whole layer) x plane x 4
-    const double top = (double)((p.kg.nz + kFZS - 1) / kFZS * kFZS) * p.kg.nx * p.kg.ny * 4.0;
+    const float* src = p.d_masked;
     // one launch per run of consecutive samples that take the same form
     for (int a = s_lo; a <= s_hi;) {
       int b = a, ng = 0;
@@ -808,20 +874,19 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
       }
       if (ng > 0) {
         const dim3 grid(8 * ((n_tiles + 7) / 8) * ng);
-#define DC_FP1(C, Z, TI)                                                                                        \
-  hipLaunchKernelGGL((k_cone_fp<T, C, Z, TI>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, \
+#define DC_FP1(Z, TI)                                                                                        \
+  hipLaunchKernelGGL((k_cone_fp<T, Z, TI>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, \
                      nv, tiles_u, n_tiles, p.cone_qmax, gmax, p.d_first, a, b, ng)
-#define DC_FP(C, Z)                                  \
-  do {                                               \
-    if (TIr == 16) DC_FP1(C, Z, 16);                 \
-    else if (TIr == 24) DC_FP1(C, Z, 24);            \
-    else DC_FP1(C, Z, 20);                           \
+#define DC_FP(Z)                                  \
+  do {                                            \
+    if (TIr == 16) DC_FP1(Z, 16);                 \
+    else if (TIr == 24) DC_FP1(Z, 24);            \
+    else DC_FP1(Z, 20);                           \
   } while (0)
-        const bool clamp = top >= 4294967296.0;
         switch (p.cone_form[a]) {
-          case kConeZinv: if (clamp) DC_FP(true, kConeZinv); else DC_FP(false, kConeZinv); break;
-          case kConeNewton: if (clamp) DC_FP(true, kConeNewton); else DC_FP(false, kConeNewton); break;
-          default: if (clamp) DC_FP(true, kConeGeneral); else DC_FP(false, kConeGeneral); break;
+          case kConeZinv: DC_FP(kConeZinv); break;
+          case kConeNewton: DC_FP(kConeNewton); break;
+          default: DC_FP(kConeGeneral); break;
         }
 #undef DC_FP
 #undef DC_FP1

@@ -50,6 +50,10 @@ struct KGrid {
 
 // Plan: host copy of the geometry plus small device tables.
 
+// z-segment length of the cone adjoint: its gather reads the gradient in bricks of
+// this many consecutive slices (nz rounded up to a multiple of it, zero-padded)
+static constexpr int kConeBrick = 16;
+
 struct Plan {
   int device = 0;
   dc_grid grid{};
@@ -85,9 +89,10 @@ struct Plan {
   // max |Gf| of the cone adjoint (float bits, reduced with integer atomicMax).  Calls
   // on one plan must therefore be ordered on one stream.
   unsigned* d_scratch = nullptr; // [V + S]
-  // volume-sized scratch for dc_cone_bp_adjoint with a ReLU mask: Gf * [f > 0]
-  // is formed once so the gather reads one array instead of two
-  float* d_masked = nullptr;     // [S][nz][ny][nx]
+  // volume-sized scratch for dc_cone_bp_adjoint: Gf (times [f > 0] with a ReLU
+  // mask) rewritten once in z-bricks of kConeBrick voxels, zero-padded, which the
+  // gather reads as contiguous 64-byte segments
+  float* d_masked = nullptr;     // [S][ceil(nz/16)][ny][nx][16]
   int n_chunks = 0;
   int splat_kc = 0;              // max angles per chunk
   int splat_max_terms = 0;       // max pixels that share one (angle, bin)

@@ -122,10 +122,10 @@ def test_smoothing_arguments_are_checked_on_the_host(P):
             P.dc_smooth_weights(plan, M, M, sigma, radius)
 
 
-def test_wide_shallow_volume_uses_the_clamped_gather(P):
-    """An 8200 x 8192 x 1 volume: a 16-slice segment's byte offsets would pass 2^32,
-    so the cone adjoint reads with clamped indices instead of the buffer range
-    check.  The slice sits 100 mm above the orbit plane, so rays cross it
+def test_wide_shallow_volume_in_the_cone_adjoint(P):
+    """An 8200 x 8192 x 1 volume: the cone adjoint's z-bricks (16 slices, 15 of
+    them padding here) span more than 2^32 bytes, so brick offsets must be formed
+    in 64 bits.  The slice sits 100 mm above the orbit plane, so rays cross it
     obliquely and few voxel centres share a detector cell.  Checked by the
     adjoint identity with the (oracle-tested) cone BP."""
     g = synth.Grid(nu=704, nv=128, du=1.0, dv=4.0, n_theta=8, n_s=synth.radon_bins(704, 128), ds=1.0,
