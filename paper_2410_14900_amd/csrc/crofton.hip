@@ -9,9 +9,13 @@
 // sinusoid the plane function F(tau) = a(tau).theta - d is sampled on a fixed grid
 // (a table of points built once per call), each sign change between neighbouring
 // samples brackets a crossing, and 80 bisection steps on the analytic curve
-// refine it.  The samples are staged in LDS in tiles shared by the workgroup's
-// 256 entries of one view; brackets are kept per thread in LDS and refined after
-// the scan, so the lanes of a wave bisect together instead of one bracket at a time.
+// refine it.  The scan skips samples that cannot change sign: |F'| <= |a'| <= L =
+// R sqrt(1 + (phi_max f)^2), so from a sample with |F| > L k h (h the sample step)
+// the next k samples keep its sign (a margin of 1e-6 covers the rounding of the
+// table and of the dot products); every sign change the full scan would see is
+// still found, in the same bracket.  Brackets are kept per thread in LDS and
+// refined after the scan, so the lanes of a wave bisect together instead of one
+// bracket at a time.
 #include <cmath>
 
 #include "dc_internal.h"
@@ -19,8 +23,8 @@
 namespace dc {
 
 static constexpr int kCrofMaxSegs = 16;
-static constexpr int kCrofTile = 256;       // staged samples per LDS tile
 static constexpr int kCrofBrackets = 16;    // brackets kept per thread and sinusoid segment
+static constexpr double kCrofSkipMargin = 1e-6;   // mm: far above the rounding of F on the table
 static constexpr int kCrofBisect = 80;
 static constexpr double kTwoPi = 6.283185307179586;   // 2 pi rounded to double
 
@@ -139,12 +143,11 @@ __global__ void k_crofton_samples(CrofArgs A, double* __restrict__ table) {
 __global__ __launch_bounds__(256) void k_crofton(CrofArgs A, const double* __restrict__ frame,
                                                  const double* __restrict__ table, float* __restrict__ M,
                                                  int n_theta, int n_s, int v0) {
-  __shared__ double sP[kCrofTile][3];
   __shared__ int sBr[kCrofBrackets][256];
   const int v = v0 + blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = e < n_theta * n_s;
-  const int k = live ? e / n_s : 0, m = live ? e - k * n_s : 0;
+  if (e >= n_theta * n_s) return;   // no barriers below: every thread works alone
+  const int k = e / n_s, m = e - k * n_s;
   // view frame and the normal theta of this (angle, bin)
   const double* F = frame + 12 * v;
   const double lx[3] = {F[6], F[7], F[8]}, ly[3] = {F[9], F[10], F[11]};
@@ -209,35 +212,33 @@ __global__ __launch_bounds__(256) void k_crofton(CrofArgs A, const double* __res
       const int n = s.n_samp;
       const double step = kTwoPi / n;
       const double* P = table + s.samp;
+      // L h, with a relative margin for the rounding of L itself
+      const double lh = A.R * sqrt(1.0 + (s.phi_max * s.freq) * (s.phi_max * s.freq)) * step * (1.0 + 1e-9);
+      auto sample = [&](int j) { return P[3ll * j] * th[0] + P[3ll * j + 1] * th[1] + P[3ll * j + 2] * th[2] - d; };
       int nbr = 0;
-      double f_first = 0.0, f_prev = 0.0;
-      for (int j0 = 0; j0 < n; j0 += kCrofTile) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < kCrofTile && j0 + q < n; q += blockDim.x) {
-          sP[q][0] = P[3ll * (j0 + q)];
-          sP[q][1] = P[3ll * (j0 + q) + 1];
-          sP[q][2] = P[3ll * (j0 + q) + 2];
-        }
-        __syncthreads();
-        const int jn = min(kCrofTile, n - j0);
-        for (int q = 0; q < jn; ++q) {
-          const double f = sP[q][0] * th[0] + sP[q][1] * th[1] + sP[q][2] * th[2] - d;
-          const int j = j0 + q;
-          if (j == 0) {
-            f_first = f;
-          } else if (sgn(f_prev) * sgn(f) <= 0) {
-            // bracket [tau_{j-1}, tau_j]
-            if (nbr < kCrofBrackets) {
-              sBr[nbr][threadIdx.x] = (j - 1) * 2 + (f_prev <= 0.0 ? 1 : 0);
-            } else if (live) {
-              const double r = bisect(s, A.R, th, d, s.p0 + (j - 1 + 0.5) * step, s.p0 + (j + 0.5) * step,
-                                      f_prev <= 0.0);
-              den += seg_weight(s, A, r, th);
-            }
-            ++nbr;
+      const double f_first = sample(0);
+      double f_prev = f_first;   // the last sample looked at (or one of the same sign)
+      int j = 0;
+      while (j + 1 < n) {
+        // samples j+1 .. j+skip keep the sign of f_prev: no bracket among them
+        const double room = (fabs(f_prev) - kCrofSkipMargin) / lh;
+        const int skip = room >= 1.0 ? (int)fmin(room, (double)(n - 1 - j)) : 0;
+        j += skip;
+        if (j + 1 >= n) break;   // the last sample has f_prev's sign
+        ++j;
+        const double f = sample(j);
+        if (sgn(f_prev) * sgn(f) <= 0) {
+          // bracket [tau_{j-1}, tau_j]; sample j-1 has f_prev's sign
+          if (nbr < kCrofBrackets) {
+            sBr[nbr][threadIdx.x] = (j - 1) * 2 + (f_prev <= 0.0 ? 1 : 0);
+          } else {
+            const double r = bisect(s, A.R, th, d, s.p0 + (j - 1 + 0.5) * step, s.p0 + (j + 0.5) * step,
+                                    f_prev <= 0.0);
+            den += seg_weight(s, A, r, th);
           }
-          f_prev = f;
+          ++nbr;
         }
+        f_prev = f;
       }
       // refine the kept brackets (lanes bisect together)
       const int kept = min(nbr, kCrofBrackets);
@@ -257,7 +258,6 @@ __global__ __launch_bounds__(256) void k_crofton(CrofArgs A, const double* __res
       }
     }
   }
-  if (!live) return;
   double tv[3];
   seg_tangent(S, A.R, tau_v, tv);
   const double num = ipow(fabs(dot3(tv, th)), A.m_exp) * seg_taper(S, tau_v, A.taper, A.c_floor);
