@@ -328,25 +328,29 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
           if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
       } else {
-        const ColumnMap c = column_map(proj + 12 * v, ix, iy, iz0);
+        // numerators about iu0 + 1/2, jv0 + 1/2: n r = u - iu0 - 1/2 (and likewise v)
+        const float zd = (float)proj[12 * v + 2];
+        const ColumnMapF c = column_map_fp<FORM == kConeNewton>(proj + 12 * v, ix, iy, iz0, 1.0f, zd,
+                                                                (float)proj[12 * v + 6], (float)proj[12 * v + 10]);
         const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
-        // kConeNewton: 1/den by one Newton step from the previous voxel's reciprocal
-        // (den moves by at most 2.5e-4 of itself per voxel step, so the step's error,
-        // that change squared, is below float rounding): two FMAs instead of a
-        // quarter-rate reciprocal
-        float r = __builtin_amdgcn_rcpf(c.den);
+        // kConeNewton (den moves by at most 2.5e-4 of itself per voxel step): 1/den
+        // along the column is its quadratic Taylor polynomial about the first voxel,
+        // whose remainder is below (7 x 2.5e-4)^3 of it, far below float rounding
+        float r0 = __builtin_amdgcn_rcpf(c.den);
+        r0 = fmaf(r0, fmaf(-c.den, r0, 1.0f), r0);
+        const float r1 = -r0 * r0 * zd, r2 = -r1 * r0 * zd;   // 1/den = r0 + r1 z + r2 z^2
 #pragma unroll
         for (int z = 0; z < kZC; ++z) {
-          if (z > 0) {
-            const float den = fmaf((float)z, c.dden, c.den);
-            r = FORM == kConeNewton ? fmaf(r, fmaf(-den, r, 1.0f), r) : __builtin_amdgcn_rcpf(den);
-          }
-          const float u = fmaf((float)z, c.ldu, c.lu) * r;
-          const float w = fmaf((float)z, c.ldv, c.lv) * r;
-          // floor by rounding u - 1/2 with the 1.5 * 2^23 trick (an exact integer u may
-          // give the cell below with fu = 1: the same value, inside the box margin)
-          const float yu = (u - 0.5f) + kRoundMagic, yw = (w - 0.5f) + kRoundMagic;
-          const float fu = u - (yu - kRoundMagic), fw = w - (yw - kRoundMagic);
+          const float r = z == 0 ? r0
+                          : FORM == kConeNewton ? fmaf((float)z, r1, fmaf((float)(z * z), r2, r0))
+                                                : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
+          const float nu = z == 0 ? c.lu : fmaf((float)z, c.ldu, c.lu);
+          const float nw = z == 0 ? c.lv : fmaf((float)z, c.ldv, c.lv);
+          // one fused rounding with the 1.5 * 2^23 trick gives the cell floor(u) (an
+          // exact integer u may give the cell below with fu = 1: the same value,
+          // inside the box margin), a second fused form the fraction
+          const float yu = fmaf(nu, r, kRoundMagic), yw = fmaf(nw, r, kRoundMagic);
+          const float fu = fmaf(nu, r, kRoundMagic - yu) + 0.5f, fw = fmaf(nw, r, kRoundMagic - yw) + 0.5f;
           const int i = oi + (int)(__float_as_uint(yu) - kRoundMagicBits);
           const int j = oj + (int)(__float_as_uint(yw) - kRoundMagicBits);
           const int q = __mul24(j, cur.w) + i;

@@ -116,8 +116,10 @@ def test_cone_blocks_and_tiles(P, case):
         outs.append(f)
     # the same arithmetic per voxel, unless one block's footprint is too large to
     # stage (fine detectors) and its taps take the direct form with a reciprocal
-    # per voxel: then the two agree to float32 rounding
-    assert rel(host(outs[0]), host(outs[1])) < 2e-6
+    # per voxel: then the two agree to float32 rounding of the tap positions, which
+    # on the 0.3 mm detector lie up to ~40 pixels from the column's anchor (one
+    # ulp of 1/den moves them by ~4e-6 pixel), i.e. to the float32 bar
+    assert rel(host(outs[0]), host(outs[1])) < TOL32
     Gf, fr = synth.rand_array((g.nz, g.ny, g.nx), 84), synth.rand_array((g.nz, g.ny, g.nx), 85)
     ref = O.cone_bp_adjoint(Gf.astype(np.float64), g, views, relu_f=fr)
     outs = []
