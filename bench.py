@@ -71,10 +71,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (13_962_975_281 + 201_420_895,
-                                 "93fe76bc13d75f123fc33fa7d80cd39cfe186f3e2b24dd9ae4966881990dc0c5"),
-    ("weight_radon", "f32"): (1_072_313_956 + 521_261_375,
-                              "83c4b9a057877df0360251fe1f0ff26998c99361a5354acbecc3532bd45d56e7"),
+    ("cone_bp_adjoint", "f32"): (7_044_110_466 + 693_005_611,
+                                 "d960688594501180ca11c482875623a5d6de272a73fc6dec14f1e22937cf39de"),
+    ("weight_radon", "f32"): (1_044_930_099 + 518_987_008,
+                              "6c9fb5613d7aab750a10c506b544e251cff35e4b951234f933d7e7371ecf51cc"),
 }
 
 
