@@ -596,7 +596,8 @@ def main():
     dom = max(r["kern"], key=r["kern"].get)
     units, byts = r["work"][dom]
     t = r["kern"][dom] * 1e-3
-    meas = MEASURED_TRAFFIC.get((dom, main_store))
+    # measured on the sinusoidal C2 step only
+    meas = MEASURED_TRAFFIC.get((dom, main_store)) if args.orbit == "sinusoid" else None
     traffic = meas[0] if meas and meas[1] == kernel_sources_digest(dom) else None
     if dom.startswith("filter"):
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(byts / t / 1e9, 1), "peak": HBM_PEAK_GBS,
