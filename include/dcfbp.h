@@ -184,7 +184,7 @@ typedef struct {
   int32_t splat_max_terms;   /* bound on the pixels whose bin floor(t) is one bin, on one angle */
   int32_t splat_checked;     /* 1 if a pixel may fall outside bins [-1, n_s): the range-checked splat */
   int32_t interp_window;     /* detector-BP window: sinogram intervals staged per angle and pixel tile */
-  int32_t interp_local;      /* 1 if that window takes the midpoint-local tap form (wide windows) */
+  int32_t interp_local;      /* 1 if that window takes the fixed-point position tap form (wide windows) */
   int32_t cone_max_terms;    /* bound on the voxel centres projecting into one detector cell of one view */
   int32_t bp_stage;          /* detector pixels each cone-BP thread stages per view (0: taps from memory) */
   int32_t cone_form;         /* 0: reciprocal per voxel, 1: Newton step along z, 2: z-invariant columns */

@@ -52,9 +52,17 @@ static uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
   return h;
 }
 
+template <typename T>
+static uint64_t fnv1a_value(uint64_t h, const T& v) {
+  return fnv1a(h, &v, sizeof v);
+}
+
 static std::string geometry_key(const Plan& p) {
   uint64_t h = 1469598103934665603ull;
-  h = fnv1a(h, &p.grid, sizeof(p.grid));
+  // field by field: dc_grid has padding between its int and double members
+  const dc_grid& g = p.grid;
+  for (int32_t v : {g.nu, g.nv, g.n_theta, g.n_s, g.nx, g.ny, g.nz}) h = fnv1a_value(h, v);
+  for (double v : {g.du, g.dv, g.ds, g.vx, g.vy, g.vz, g.ox, g.oy, g.oz}) h = fnv1a_value(h, v);
   h = fnv1a(h, &p.n_views, sizeof(p.n_views));
   h = fnv1a(h, p.first.data(), p.first.size() * sizeof(int));
   h = fnv1a(h, p.views.data(), p.views.size() * sizeof(dc_view));

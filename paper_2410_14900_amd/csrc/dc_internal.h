@@ -98,7 +98,7 @@ struct Plan {
   int splat_max_terms = 0;       // max pixels that share one (angle, bin)
   int splat_checked = 1;         // 0 when every pixel lands on bins [-1, n_s) for all angles
   int interp_wl = 0;             // LDS window length for the interpolating kernels
-                                 // (above kInterpLocalAbove: the midpoint-local tap form)
+                                 // (above kInterpLocalAbove: the fixed-point position tap form)
   // fixed-point scales: a sum of the splat (cone FP) holds terms of at most qmax
   // units, qmax = fixed_point_qmax(splat_max_terms (cone_max_terms))
   float splat_qmax = 0.f, cone_qmax = 0.f;
