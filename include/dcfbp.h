@@ -187,7 +187,7 @@ typedef struct {
   int32_t interp_local;      /* 1 if that window takes the fixed-point position tap form (wide windows) */
   int32_t cone_max_terms;    /* bound on the voxel centres projecting into one detector cell of one view */
   int32_t bp_stage;          /* detector pixels each cone-BP thread stages per view (0: taps from memory) */
-  int32_t cone_form;         /* 0: reciprocal per voxel, 1: Newton step along z, 2: z-invariant columns */
+  int32_t cone_form;         /* 0: reciprocal per voxel, 1: 1/U quadratic in z, 2: z-invariant columns */
   int32_t bp_block[3];       /* cone-BP voxel block (x, y, z) */
   int32_t interp_tile[2];    /* detector-BP pixel tile (u, v) */
   float   splat_qmax;        /* units of the largest splat term */
@@ -244,9 +244,10 @@ dc_status dc_detector_bp_adjoint(dc_plan plan, const void* GgF, dc_dtype tF, voi
  * The plan evaluates each sample's projections (here and in dc_cone_bp_adjoint)
  * in one of three forms chosen from its geometry: per voxel column when no view's
  * depth U or detector u coordinate varies along z (detector v axis along z); with
- * 1/U iterated by a Newton step along z when U changes by at most 2.5e-4 of itself
- * per voxel step; with a reciprocal per voxel otherwise.  The forms agree to
- * float32 rounding, and each is deterministic. */
+ * 1/U taken along z as its quadratic Taylor polynomial about a segment's first
+ * voxel when U changes by at most 2.5e-4 of itself per voxel step; with a
+ * reciprocal per voxel otherwise.  The forms agree to float32 rounding, and each
+ * is deterministic. */
 dc_status dc_cone_bp(dc_plan plan, const void* gF, dc_dtype tF, float* f, int32_t accumulate,
                      int32_t relu, int32_t v0, int32_t nv, hipStream_t stream);
 /* Exact transpose of dc_cone_bp (cone-beam forward projection of Gf):

@@ -86,14 +86,16 @@ static dc_status upload_tables(Plan* p, const dc_view* views, const KernelShape&
   const dc_status st = plan_tables(g, views, n, p->first.data(), n_samples, ks, &hp, &err);
   if (st != DC_OK) return fail(st, err);
   // upload into new buffers; the plan keeps its old tables unless all succeed
-  enum { kAng, kTrig, kView, kFrame, kProj, kRmax2, kChunks, kFirst, kN };
+  enum { kAng, kTrig, kView, kFrame, kProj, kRmax2, kChunks, kFirst, kForm, kN };
   void* fresh[kN] = {};
+  const std::vector<int> forms(hp.cone_form.begin(), hp.cone_form.end());
   const void* src[kN] = {hp.ang.data(), hp.trig.data(), hp.vf.data(), hp.frame.data(),
-                         hp.proj.data(), hp.rmax2.data(), hp.chunks.data(), p->first.data()};
+                         hp.proj.data(), hp.rmax2.data(), hp.chunks.data(), p->first.data(), forms.data()};
   const size_t bytes[kN] = {hp.ang.size() * sizeof(double), hp.trig.size() * sizeof(float),
                             hp.vf.size() * sizeof(float), hp.frame.size() * sizeof(double),
                             hp.proj.size() * sizeof(double), hp.rmax2.size() * sizeof(float),
-                            hp.chunks.size() * sizeof(int), p->first.size() * sizeof(int)};
+                            hp.chunks.size() * sizeof(int), p->first.size() * sizeof(int),
+                            forms.size() * sizeof(int)};
   hipError_t e = hipSuccess;
   for (int i = 0; i < kN && e == hipSuccess; ++i) {
     e = hipMalloc(&fresh[i], bytes[i]);
@@ -105,7 +107,8 @@ static dc_status upload_tables(Plan* p, const dc_view* views, const KernelShape&
     return fail(e == hipErrorOutOfMemory ? DC_ENOMEM : DC_EHIP, std::string("plan upload: ") + hipGetErrorString(e));
   }
   // the old tables may still be read by queued kernels: let the device drain first
-  void* old[kN] = {p->d_ang, p->d_trig, p->d_view, p->d_frame, p->d_proj, p->d_rmax2, p->d_chunks, p->d_first};
+  void* old[kN] = {p->d_ang, p->d_trig, p->d_view, p->d_frame, p->d_proj, p->d_rmax2, p->d_chunks, p->d_first,
+                   p->d_form};
   bool any_old = false;
   for (void* q : old) any_old = any_old || q;
   if (any_old) {
@@ -121,6 +124,7 @@ static dc_status upload_tables(Plan* p, const dc_view* views, const KernelShape&
   p->d_rmax2 = (float*)fresh[kRmax2];
   p->d_chunks = (int4*)fresh[kChunks];
   p->d_first = (int*)fresh[kFirst];
+  p->d_form = (int*)fresh[kForm];
   p->shape = ks;
   p->shape.splat_kc = hp.splat_kc;
   p->interp_wl = hp.interp_wl;
@@ -137,8 +141,8 @@ static dc_status upload_tables(Plan* p, const dc_view* views, const KernelShape&
 }
 
 static void free_plan(Plan* p) {
-  void* ptrs[] = {p->d_ang,    p->d_trig,  p->d_view,    p->d_frame,  p->d_proj,
-                  p->d_rmax2,  p->d_chunks, p->d_first, p->d_scratch, p->d_masked};
+  void* ptrs[] = {p->d_ang,    p->d_trig,  p->d_view,    p->d_frame,  p->d_proj,   p->d_rmax2,
+                  p->d_chunks, p->d_first, p->d_form,    p->d_scratch, p->d_masked};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;

@@ -19,6 +19,7 @@
 // column's projection, so the float32 per-voxel coordinates stay small and
 // their rounding far below 1e-5 pixel.
 #include <algorithm>
+#include <type_traits>
 
 #include "dc_internal.h"
 
@@ -26,6 +27,9 @@ namespace dc {
 
 // Block: kBX x BY x kZC voxels, BY = 16 or 32 (the plan's knob), kBX BY threads.
 static constexpr int kBX = 16, kZC = 8;
+// kernel template value for a launch over samples of different forms (ConeForm)
+static constexpr int kConeMixed = 3;
+
 static constexpr float kRoundMagic = 12582912.0f;         // 1.5 * 2^23
 static constexpr unsigned kRoundMagicBits = 0x4B400000u;  // its bit pattern
 
@@ -192,11 +196,14 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
 
 // STAGE = staged pixels per thread and view (the plan picks the smallest that
 // holds the largest footprint); STAGE == 0 selects direct global taps.  FORM
-// (staged form only) is the plan's choice for the sample (ConeForm).
+// (staged form only) is the plan's choice for the sample (ConeForm), or
+// kConeMixed: a launch over samples of different forms reads each workgroup's
+// form from `forms` (one entry per sample).
 template <typename T, int STAGE, int FORM, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
-                                                 int nv, const int* __restrict__ first, int s_lo, int nzb) {
+                                                 int nv, const int* __restrict__ first, int s_lo, int nzb,
+                                                 const int* __restrict__ forms) {
   constexpr int kBPThreads = kBX * BY;
   constexpr int kTile = STAGE > 0 ? kBPThreads * STAGE : 1;
   __shared__ float tile[2][kTile];
@@ -290,6 +297,10 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
       store_stage(0);
     }
     __syncthreads();
+    // the view loop for one form F (kConeMixed takes the sample's form at run time:
+    // one uniform branch per workgroup, the same arithmetic as the form's own kernel)
+    auto view_loop = [&](auto form_tag) __attribute__((always_inline)) {
+    constexpr int F = decltype(form_tag)::value;
     for (int v = v0; v < v0 + nv; ++v) {
       const int buf = (v - v0) & 1;
       Box nxt{0, 0, 0, 0};
@@ -311,7 +322,7 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
       // LDS.  Nothing depends on those reads: LDS loads never fault (past the
       // allocation they return 0, inside it any value), and the results of those
       // lanes and slices are never written (the guards at the end).
-      if constexpr (FORM == kConeZinv) {
+      if constexpr (F == kConeZinv) {
         const ColumnMapZ c = column_map_z(proj + 12 * v, ix, iy, iz0);
         const float* tc = t + (c.i - cur.i_lo);
         // row index = bits(round(w - 1/2) + 1.5 * 2^23) - bias, in tile rows
@@ -330,10 +341,10 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
       } else {
         // numerators about iu0 + 1/2, jv0 + 1/2: n r = u - iu0 - 1/2 (and likewise v)
         const float zd = (float)proj[12 * v + 2];
-        const ColumnMapF c = column_map_fp<FORM == kConeNewton>(proj + 12 * v, ix, iy, iz0, 1.0f, zd,
+        const ColumnMapF c = column_map_fp<F == kConeQuadratic>(proj + 12 * v, ix, iy, iz0, 1.0f, zd,
                                                                 (float)proj[12 * v + 6], (float)proj[12 * v + 10]);
         const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
-        // kConeNewton (den moves by at most 2.5e-4 of itself per voxel step): 1/den
+        // kConeQuadratic (den moves by at most 2.5e-4 of itself per voxel step): 1/den
         // along the column is its quadratic Taylor polynomial about the first voxel,
         // whose remainder is below (7 x 2.5e-4)^3 of it, far below float rounding
         float r0 = __builtin_amdgcn_rcpf(c.den);
@@ -342,7 +353,7 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
 #pragma unroll
         for (int z = 0; z < kZC; ++z) {
           const float r = z == 0 ? r0
-                          : FORM == kConeNewton ? fmaf((float)z, r1, fmaf((float)(z * z), r2, r0))
+                          : F == kConeQuadratic ? fmaf((float)z, r1, fmaf((float)(z * z), r2, r0))
                                                 : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
           const float nu = z == 0 ? c.lu : fmaf((float)z, c.ldu, c.lu);
           const float nw = z == 0 ? c.lv : fmaf((float)z, c.ldv, c.lv);
@@ -365,6 +376,15 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
       if (more) store_stage(buf ^ 1);
       __syncthreads();
       cur = nxt;
+    }
+    };
+    if constexpr (FORM == kConeMixed) {
+      const int fs = forms[smp];
+      if (fs == kConeZinv) view_loop(std::integral_constant<int, kConeZinv>{});
+      else if (fs == kConeQuadratic) view_loop(std::integral_constant<int, kConeQuadratic>{});
+      else view_loop(std::integral_constant<int, kConeGeneral>{});
+    } else {
+      view_loop(std::integral_constant<int, FORM>{});
     }
   }
   if (ix >= g.nx || iy >= g.ny) return;
@@ -493,7 +513,7 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
 // Gf: the z-bricked (masked) gradient written by k_vol_brick.
 // FORM (ConeForm) as in the backprojection; with kConeZinv each (segment, view)
 // has one u, one tap column and one weight, and a segment whose column misses
-// the tile is skipped whole.  With kConeNewton (den changes by at most 2.5e-4 of
+// the tile is skipped whole.  With kConeQuadratic (den changes by at most 2.5e-4 of
 // itself per voxel step) 1/den along the segment is its quadratic Taylor
 // polynomial about the first voxel: the remainder is below (15 x 2.5e-4)^3 =
 // 5.3e-8 of it, float rounding, and every voxel's reciprocal is independent.
@@ -502,7 +522,8 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
                                                  const double* __restrict__ proj, const float* __restrict__ rmax2,
                                                  int v0, int nv, int tiles_u, int n_tiles, float qmax,
                                                  const unsigned* __restrict__ gmax_bits,
-                                                 const int* __restrict__ first, int s_lo, int s_hi, int ngroups) {
+                                                 const int* __restrict__ first, int s_lo, int s_hi, int ngroups,
+                                                 const int* __restrict__ forms) {
   __shared__ double sL[kFV][4][4], sNegInvA[kFV][4];
   __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
   __shared__ unsigned char sLay[kFROWS];   // z-layer of each listed row (sRow holds its y)
@@ -660,6 +681,10 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
     // bisection and then advanced by a short forward scan (rows hold ~15-30 items).
     const int per_wave = (total + 3) >> 2;
     const int qa = (threadIdx.x >> 6) * per_wave, qb = min(total, qa + per_wave);
+    // the items for one form F (kConeMixed takes the sample's form at run time:
+    // one uniform branch per batch, the same arithmetic as the form's own kernel)
+    auto items = [&](auto form_tag) __attribute__((always_inline)) {
+    constexpr int F = decltype(form_tag)::value;
     int lo = -1;
     for (int q = qa + (threadIdx.x & 63); q < qb; q += 64) {
       if (lo < 0) {
@@ -693,7 +718,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       for (int w = 0; w < nvw; ++w) {
         unsigned long long* ab = sAB[w];
         unsigned long long* ce = sCE[w];
-        if constexpr (FORM == kConeZinv) {
+        if constexpr (F == kConeZinv) {
           const ColumnMapZ c = column_map_z(proj + 12 * (va + w), ix, iy, iz0);
           const int li = c.i - (i0 - 1);
           if ((unsigned)li > (unsigned)(i1 - i0)) continue;
@@ -718,7 +743,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           continue;
         }
         const float zd = pick(zstep_d, w);
-        const ColumnMapF c = column_map_fp<FORM == kConeNewton>(proj + 12 * (va + w), ix, iy, iz0, pick(sinv, w), zd,
+        const ColumnMapF c = column_map_fp<F == kConeQuadratic>(proj + 12 * (va + w), ix, iy, iz0, pick(sinv, w), zd,
                                                                  pick(zstep_u, w), pick(zstep_v, w));
         float rr0 = __builtin_amdgcn_rcpf(c.den);
         rr0 = fmaf(rr0, fmaf(-c.den, rr0, 1.0f), rr0);   // one Newton step: a correctly rounded start
@@ -726,7 +751,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
 #pragma unroll
         for (int z = 0; z < kFZS; ++z) {
           const float rr = z == 0 ? rr0
-                           : FORM == kConeNewton ? fmaf((float)z, r1, fmaf((float)(z * z), r2, rr0))
+                           : F == kConeQuadratic ? fmaf((float)z, r1, fmaf((float)(z * z), r2, rr0))
                                                  : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
           // nu rr = u - iu0 - 1/2 (and likewise v): one fused rounding with the
           // 1.5 * 2^23 trick gives the cell floor(u) (an exact integer u may give the
@@ -755,6 +780,15 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           }
         }
       }
+    }
+    };
+    if constexpr (FORM == kConeMixed) {
+      const int fs = forms[smp];
+      if (fs == kConeZinv) items(std::integral_constant<int, kConeZinv>{});
+      else if (fs == kConeQuadratic) items(std::integral_constant<int, kConeQuadratic>{});
+      else items(std::integral_constant<int, kConeGeneral>{});
+    } else {
+      items(std::integral_constant<int, FORM>{});
     }
     __syncthreads();
   }
@@ -794,6 +828,13 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   }
 }
 
+// the form every sample in [s_lo, s_hi] takes, or kConeMixed when they differ
+static int launch_form(const Plan& p, int s_lo, int s_hi) {
+  for (int smp = s_lo + 1; smp <= s_hi; ++smp)
+    if (p.cone_form[smp] != p.cone_form[s_lo]) return kConeMixed;
+  return p.cone_form[s_lo];
+}
+
 static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0,
                                      int nv, int s_lo, int s_hi, int nzb, int form, hipStream_t s);
 
@@ -802,15 +843,8 @@ hipError_t launch_cone_bp(const Plan& p, const void* gF, dc_dtype tF, float* f, 
   int s_lo, s_hi;
   sample_span(p, v0, nv, &s_lo, &s_hi);
   const int nzb = (p.kg.nz + kZC - 1) / kZC;
-  // one launch per run of consecutive samples that take the same form
-  for (int a = s_lo; a <= s_hi;) {
-    int b = a;
-    while (b < s_hi && p.cone_form[b + 1] == p.cone_form[a]) ++b;
-    const hipError_t e = launch_cone_bp_run(p, gF, tF, f, acc, relu, v0, nv, a, b, nzb, p.cone_form[a], s);
-    if (e != hipSuccess) return e;
-    a = b + 1;
-  }
-  return hipSuccess;
+  // one launch: the samples' own form, or kConeMixed when they differ
+  return launch_cone_bp_run(p, gF, tF, f, acc, relu, v0, nv, s_lo, s_hi, nzb, launch_form(p, s_lo, s_hi), s);
 }
 
 static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF, float* f, int acc, int relu, int v0,
@@ -821,7 +855,7 @@ static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF,
     using T = decltype(t);
 #define DC_BP1(ST, Z, BY)                                                                                           \
   hipLaunchKernelGGL((k_cone_bp<T, ST, Z, BY>), grid, dim3(kBX, BY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, \
-                     relu, v0, nv, p.d_first, s_lo, nzb)
+                     relu, v0, nv, p.d_first, s_lo, nzb, p.d_form)
 #define DC_BP(ST, Z)                   \
   do {                                 \
     if (BYr == 16) DC_BP1(ST, Z, 16);  \
@@ -830,7 +864,8 @@ static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF,
 #define DC_BP_FORMS(ST)                                            \
   switch (form) {                                                  \
     case kConeZinv: DC_BP(ST, kConeZinv); break;                   \
-    case kConeNewton: DC_BP(ST, kConeNewton); break;               \
+    case kConeQuadratic: DC_BP(ST, kConeQuadratic); break;         \
+    case kConeMixed: DC_BP(ST, kConeMixed); break;                 \
     default: DC_BP(ST, kConeGeneral); break;                       \
   }
     switch (p.bp_stage) {
@@ -868,36 +903,33 @@ hipError_t launch_cone_fp(const Plan& p, const float* Gf, const float* f_relu, v
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
     const float* src = p.d_masked;
-    // one launch per run of consecutive samples that take the same form
-    for (int a = s_lo; a <= s_hi;) {
-      int b = a, ng = 0;
-      while (b < s_hi && p.cone_form[b + 1] == p.cone_form[a]) ++b;
-      for (int smp = a; smp <= b; ++smp) {
-        const int vb = std::max(v0, p.first[smp]), ve = std::min(v0 + nv, p.first[smp + 1]);
-        ng += (std::max(0, ve - vb) + kFV - 1) / kFV;
-      }
-      if (ng > 0) {
-        const dim3 grid(8 * ((n_tiles + 7) / 8) * ng);
+    // one launch: the samples' own form, or kConeMixed when they differ
+    int ng = 0;
+    for (int smp = s_lo; smp <= s_hi; ++smp) {
+      const int vb = std::max(v0, p.first[smp]), ve = std::min(v0 + nv, p.first[smp + 1]);
+      ng += (std::max(0, ve - vb) + kFV - 1) / kFV;
+    }
+    if (ng > 0) {
+      const dim3 grid(8 * ((n_tiles + 7) / 8) * ng);
 #define DC_FP1(Z, TI)                                                                                        \
   hipLaunchKernelGGL((k_cone_fp<T, Z, TI>), grid, dim3(256), 0, s, src, (T*)GgF, p.kg, p.d_proj, p.d_rmax2, v0, \
-                     nv, tiles_u, n_tiles, p.cone_qmax, gmax, p.d_first, a, b, ng)
+                     nv, tiles_u, n_tiles, p.cone_qmax, gmax, p.d_first, s_lo, s_hi, ng, p.d_form)
 #define DC_FP(Z)                                  \
   do {                                            \
     if (TIr == 16) DC_FP1(Z, 16);                 \
     else if (TIr == 24) DC_FP1(Z, 24);            \
     else DC_FP1(Z, 20);                           \
   } while (0)
-        switch (p.cone_form[a]) {
-          case kConeZinv: DC_FP(kConeZinv); break;
-          case kConeNewton: DC_FP(kConeNewton); break;
-          default: DC_FP(kConeGeneral); break;
-        }
+      switch (launch_form(p, s_lo, s_hi)) {
+        case kConeZinv: DC_FP(kConeZinv); break;
+        case kConeQuadratic: DC_FP(kConeQuadratic); break;
+        case kConeMixed: DC_FP(kConeMixed); break;
+        default: DC_FP(kConeGeneral); break;
+      }
 #undef DC_FP
 #undef DC_FP1
-        const hipError_t e2 = hipGetLastError();
-        if (e2 != hipSuccess) return e2;
-      }
-      a = b + 1;
+      const hipError_t e2 = hipGetLastError();
+      if (e2 != hipSuccess) return e2;
     }
     return hipSuccess;
   });

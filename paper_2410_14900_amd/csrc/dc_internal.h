@@ -80,11 +80,12 @@ struct Plan {
   // per-view arrays hold all samples' views, volumes one block per sample
   int n_samples = 1;
   std::vector<int> first;        // host copy, [n_samples + 1]
-  // per sample, the form of the cone kernels: kConeGeneral, kConeNewton (den varies so
-  // slowly along z that a Newton step from the previous voxel gives 1/den) or kConeZinv
+  // per sample, the form of the cone kernels: kConeGeneral, kConeQuadratic (den varies so
+  // slowly along z that 1/den is a quadratic in z over a segment) or kConeZinv
   // (no view's den or num_u has a z-term: the detector's v axis stays along z)
   std::vector<char> cone_form;
   int* d_first = nullptr;        // [n_samples + 1]
+  int* d_form = nullptr;         // [n_samples] cone_form on the device, for launches over mixed forms
   // plan-owned scratch: [0, V) per-view max |input| of the splat, [V, V + S) per-sample
   // max |Gf| of the cone adjoint (float bits, reduced with integer atomicMax).  Calls
   // on one plan must therefore be ordered on one stream.

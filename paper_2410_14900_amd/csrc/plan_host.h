@@ -33,7 +33,7 @@ static constexpr int kInterpMaxKC = 64;
 // DC_OK if the shape is one the kernels are built for (DC_EINVAL otherwise, message in *err).
 dc_status check_shape(const KernelShape& ks, std::string* err);
 
-enum ConeForm : char { kConeGeneral = 0, kConeNewton = 1, kConeZinv = 2 };
+enum ConeForm : char { kConeGeneral = 0, kConeQuadratic = 1, kConeZinv = 2 };
 
 // Largest number of voxel centres the cone adjoint may add into one accumulator
 // (one detector cell in one view); its fixed-point quantum is 2^30 / this of the

@@ -1,7 +1,7 @@
 """Batched plans on the GPU: several scans with different orbits and view counts
-share one grid and run every stage in one launch per kernel (the cone stages: one
-per run of scans of one evaluation form; the sinusoid, circle and circle+arc
-scans here take the Newton, z-invariant and plain forms).  Each result must
+share one grid and run every stage in one launch per kernel (the cone stages too:
+the sinusoid, circle and circle+arc scans here take the quadratic, z-invariant
+and plain forms, and each workgroup of the mixed launch takes its scan's).  Each result must
 be bit-identical to the same scan run through its own single-scan plan (whose
 parity with the oracle the other GPU tests establish), also for view ranges that
 cross sample boundaries, and a training step captured in a HIP graph must
