@@ -230,10 +230,10 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
       const T* img = gF + (size_t)v * npix;
 #pragma unroll
       for (int z = 0; z < kZC; ++z) {
-        const float den = fmaf((float)z, c.dden, c.den);
+        const float den = z == 0 ? c.den : fmaf((float)z, c.dden, c.den);
         const float r = __builtin_amdgcn_rcpf(den);
-        const float u = fmaf((float)z, c.ldu, c.lu) * r;
-        const float w = fmaf((float)z, c.ldv, c.lv) * r;
+        const float u = (z == 0 ? c.lu : fmaf((float)z, c.ldu, c.lu)) * r;
+        const float w = (z == 0 ? c.lv : fmaf((float)z, c.ldv, c.lv)) * r;
         const float fu0 = floorf(u), fw0 = floorf(w);
         const float fu = u - fu0, fw = w - fw0;
         const int i = c.iu0 + (int)fu0, j = c.jv0 + (int)fw0;
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
         const unsigned jbias = kRoundMagicBits - (unsigned)(c.jv0 - cur.j_lo);
 #pragma unroll
         for (int z = 0; z < kZC; ++z) {
-          const float wm = fmaf((float)z, c.dw, c.w0m);
+          const float wm = z == 0 ? c.w0m : fmaf((float)z, c.dw, c.w0m);
           const float yw = wm + kRoundMagic;
           const float fw = (wm - (yw - kRoundMagic)) + 0.5f;
           const float* r0 = tc + __umul24(__float_as_uint(yw) - jbias, (unsigned)cur.w);
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           const unsigned jbias = kRoundMagicBits - (unsigned)(c.jv0 - (j0 - 1));
 #pragma unroll
           for (int z = 0; z < kFZS; ++z) {
-            const float wm = fmaf((float)z, c.dw, c.w0m);
+            const float wm = z == 0 ? c.w0m : fmaf((float)z, c.dw, c.w0m);
             const float yw = wm + kRoundMagic;
             const int lj = (int)(__float_as_uint(yw) - jbias);
             const float x = gv[z];

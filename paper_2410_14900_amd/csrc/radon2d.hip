@@ -322,7 +322,7 @@ __global__ __launch_bounds__(TX * 8) void k_interp(const Tin* __restrict__ rows,
       const unsigned nbias = (unsigned)__float_as_int(P.w);   // window slot = bits(th + 1.5 2^23) + nbias
 #pragma unroll
       for (int h = 0; h < kTPX; ++h) {
-        const float th = fmaf((float)h, b8, th0);
+        const float th = h == 0 ? th0 : fmaf((float)h, b8, th0);   // 0 b8 + th0 is not folded
         const float y = th + kRoundMagic;
         const float2 pr = win[__float_as_uint(y) + nbias];
         acc[h] += fmaf(th, pr.y, pr.x);
