@@ -425,6 +425,68 @@ def c5_line(P, synth, args):
     return out
 
 
+# The paper's own timing of this method (its Table 4, sinusoidal orbit): one
+# reconstruction with trained weights, forward only, on an NVIDIA RTX 4080 Super,
+# against 197 s for 300 iterations of AIR (the abstract's "more than 97%").
+PAPER_FORWARD_S = 4.5
+PAPER_AIR_S = 197.0
+
+
+def paper_workload_line(P, synth, args):
+    """The paper's reconstruction workload (its Tables 1-2 and the sinusoidal-orbit
+    section): a 128 x 512 x 512 volume at 0.25 mm from 400 views of a 620 x 480
+    detector at 0.616 mm (SID 750 mm, SDD 1200 mm) on the sinusoid with a 20 degree
+    maximum tilt and frequency 5, Radon 360 x 785.  One forward reconstruction
+    (weighted Radon, filter, detector BP, cone BP + ReLU) on synthetic projections of
+    that shape, timed with HIP events; the paper's own figure is quoted beside it as
+    context (other hardware, its trained weights and data)."""
+    import torch
+    grid = synth.Grid(nu=620, nv=480, du=0.616, dv=0.616, n_theta=360, n_s=synth.radon_bins(620, 480), ds=0.616,
+                      nx=512, ny=512, nz=128, vx=0.25, vy=0.25, vz=0.25)
+    views = synth.sinusoid_orbit(400, 750.0, 1200.0, phi_max=math.radians(20.0), periods=5)
+    plan = P.Plan(grid, views)
+    if not args.no_autotune:
+        plan.autotune()
+    V, nvox = len(views), grid.nx * grid.ny * grid.nz
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    g = torch.rand((V, grid.nv, grid.nu), device="cuda", generator=gen)
+    M = torch.full((V,) + plan.sino_shape, 0.5, device="cuda")
+    R = torch.empty((V,) + plan.sino_shape, device="cuda")
+    H = torch.empty_like(R)
+    gF = torch.empty_like(g)
+    f = torch.empty(plan.vol_shape, device="cuda")
+
+    def forward():
+        P.dc_weight_radon(plan, g, R)
+        P.dc_filter(plan, R, M, H)
+        P.dc_detector_bp(plan, H, gF)
+        P.dc_cone_bp(plan, gF, f, relu=True)
+
+    for _ in range(max(1, args.warmup)):
+        forward()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n = max(3, args.steps)
+    a.record()
+    for _ in range(n):
+        forward()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / n
+    out = {"workload": "the paper's: sinusoidal orbit (20 deg, f = 5), 400 views, 620x480 detector @0.616 mm, "
+                       "Radon 360x785, 128x512x512 volume @0.25 mm, one forward reconstruction",
+           "knobs": plan.knobs(), "ms": round(ms, 3), "value": nvox * V / (ms * 1e-3), "unit": "voxel-view updates/s",
+           "paper_context": {"seconds": PAPER_FORWARD_S, "gpu": "NVIDIA RTX 4080 Super",
+                             "value": nvox * V / PAPER_FORWARD_S,
+                             "air_seconds": PAPER_AIR_S,
+                             "source": "the paper's Table 4 (forward with trained weights; 300 AIR iterations 197 s)"}}
+    log("paper workload: %.2f ms per forward reconstruction (the paper: %.1f s on an RTX 4080 Super)"
+        % (ms, PAPER_FORWARD_S))
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def crofton_baseline(P, plan, views, g, target):
     """The analytic smooth Crofton weight of eq. 9 generated on the device for all
     views (one timed call after a warm-up), and the reconstruction error it gives
@@ -474,6 +536,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 8-scan measurement")
     ap.add_argument("--no-c3", action="store_true", help="skip the circle-plus-arc (C3) line")
     ap.add_argument("--no-c5", action="store_true", help="skip the full C-arm scale (C5) line")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the forward reconstruction of the paper's own workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plans' default knobs")
     ap.add_argument("--orbit", choices=["sinusoid", "circle"], default="sinusoid",
                     help="the C2 grid on its sinusoidal orbit (default) or on a 496-view circle")
@@ -647,6 +711,8 @@ def main():
     if not args.no_c3:
         out["c3"] = c3_line(P, synth, args)
         torch.cuda.empty_cache()
+    if not args.no_paper:
+        out["paper_workload"] = paper_workload_line(P, synth, args)
     if not args.no_c5:
         del plan
         torch.cuda.empty_cache()
