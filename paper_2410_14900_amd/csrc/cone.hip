@@ -637,10 +637,13 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
           const double a = L[0];
           const double c0 = fma(L[1], (double)iy, L[3]);
           const double cm = fmax(fma(L[2], zlo, c0), fma(L[2], zhi, c0));
-          const double xb = cm * sNegInvA[w][k];      // L_k = a x + cm crosses zero here
-          if (a > 0.0) xlo = fmax(xlo, ceil(xb) - 1.0);
-          else if (a < 0.0) xhi = fmin(xhi, floor(xb) + 1.0);
-          else if (cm < 0.0) empty = true;
+          // L_k = a x + cm >= -eta up to xb: eta = 0.01 in L's units (pixel x den)
+          // keeps at least 0.01 pixel of slack (den <= 1) over the per-voxel float
+          // test, whose error stays near 1e-5 pixel
+          const double xb = (cm + 0.01) * sNegInvA[w][k];
+          if (a > 0.0) xlo = fmax(xlo, ceil(xb));
+          else if (a < 0.0) xhi = fmin(xhi, floor(xb));
+          else if (cm < -0.01) empty = true;
         }
         if (!empty && xlo <= xhi) {
           ulo = fmin(ulo, xlo);
