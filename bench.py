@@ -71,10 +71,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (7_044_110_466 + 693_005_611,
-                                 "d960688594501180ca11c482875623a5d6de272a73fc6dec14f1e22937cf39de"),
-    ("weight_radon", "f32"): (1_044_930_099 + 518_987_008,
-                              "6c9fb5613d7aab750a10c506b544e251cff35e4b951234f933d7e7371ecf51cc"),
+    ("cone_bp_adjoint", "f32"): (6_812_742_612 + 693_006_795,
+                                 "4b6a82bd04a850b3ec4ab1ce2d7bde2d1a7df1077c497b8e0b03c5b47657a618"),
+    ("weight_radon", "f32"): (1_045_762_554 + 518_984_960,
+                              "8e81c328698c0b2ef1043ea0c781994b3d94463deba672ab69af8d380bdaa32e"),
 }
 
 
