@@ -441,9 +441,7 @@ def paper_workload_line(P, synth, args):
     that shape, timed with HIP events; the paper's own figure is quoted beside it as
     context (other hardware, its trained weights and data)."""
     import torch
-    grid = synth.Grid(nu=620, nv=480, du=0.616, dv=0.616, n_theta=360, n_s=synth.radon_bins(620, 480), ds=0.616,
-                      nx=512, ny=512, nz=128, vx=0.25, vy=0.25, vz=0.25)
-    views = synth.sinusoid_orbit(400, 750.0, 1200.0, phi_max=math.radians(20.0), periods=5)
+    grid, views = synth.paper_geometry()
     plan = P.Plan(grid, views)
     if not args.no_autotune:
         plan.autotune()

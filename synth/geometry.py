@@ -206,7 +206,7 @@ def random_nn_orbit(n_views, sid, sdd, tilt_deg=10.0, seed=0):
 
 # ---------------------------------------------------------------------------
 # Workloads.  C1..C5 are the five scan configurations the library is measured
-# and parity-tested on; "paper" is the paper's own geometry (Tables 1 and 2).
+# and parity-tested on; paper_geometry() below is the paper's own (Tables 1 and 2).
 # ---------------------------------------------------------------------------
 CONFIGS = {
     "C1": dict(orbit="circle", n_views=90, vol=32, vox=1.0, det=64, pitch=1.0, n_theta=180,
@@ -241,6 +241,18 @@ def config_geometry(name: str, n_views: int | None = None):
             views = circle_arc_orbit(na, n_views - na, c["sid"], c["sdd"], c["tilt"])
     else:
         raise ValueError(c["orbit"])
+    return grid, views
+
+
+def paper_geometry():
+    """The paper's reconstruction geometry (its Tables 1 and 2 and the sinusoidal
+    orbit section): a 128 x 512 x 512 volume (z, y, x) of 0.25 mm voxels, 400 views
+    of a 620 x 480 detector with 0.616 mm pixels, SID 750 mm, SDD 1200 mm, the
+    sinusoid with a 20 degree maximum tilt and frequency 5, and a Radon grid of 360
+    angles by 785 bins of 0.616 mm."""
+    grid = Grid(nu=620, nv=480, du=0.616, dv=0.616, n_theta=360, n_s=radon_bins(620, 480), ds=0.616,
+                nx=512, ny=512, nz=128, vx=0.25, vy=0.25, vz=0.25)
+    views = sinusoid_orbit(400, 750.0, 1200.0, phi_max=math.radians(20.0), periods=5)
     return grid, views
 
 
