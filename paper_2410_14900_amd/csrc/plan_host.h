@@ -44,14 +44,15 @@ static constexpr int kMaxInterpWindow = 512;
 
 // Integer units given to the largest term of a fixed-point sum (the splat's a
 // and b sums, the cone FP's four tap sums) when at most max_terms terms share
-// one 32-bit accumulator half: max_terms terms of at most qmax + 1/2 units each
-// (the term rounded to an integer) keep the half's magnitude below
-// 2^30 + max_terms / 2 < 2^31, and every term stays below 2^21 units, where the
-// kernels' float rounding trick (adding 1.5 2^23) is exact.  Computed in float32
-// on the host and passed to the kernels, so bounds and kernels share one value.
+// one signed 32-bit accumulator half: max_terms terms of at most qmax + 1 units
+// each (the term rounded to an integer, with a unit to spare for the float
+// rounding of its scale) keep the half's magnitude at most 2^31 - 1, and every
+// term stays below 2^21 units, where the kernels' float rounding trick (adding
+// 1.5 2^23) is exact.  Computed on the host and passed to the kernels as a float
+// (an integer below 2^21, exact), so bounds and kernels share one value.
 inline float fixed_point_qmax(int max_terms) {
-  const float q = std::floor(2147483647.0f / (float)(max_terms + 1) * 0.5f);
-  return q < 2097152.0f ? q : 2097152.0f;
+  const double q = std::floor(2147483647.0 / (double)std::max(max_terms, 1)) - 1.0;
+  return q < 2097152.0 ? (float)q : 2097152.0f;
 }
 
 struct HostPlan {

@@ -181,13 +181,13 @@ def test_plan_bounds_hold_against_brute_force_counts(P, name):
     assert b["splat_max_terms"] <= 2 * n_pix + g.nv        # not loose by more than the per-line slack
     if not inside:
         assert b["splat_checked"] == 1
-    # a 32-bit accumulator half never overflows: terms of at most qmax + 1/2 units
-    assert n_pix * (b["splat_qmax"] + 0.5) < 2 ** 31
+    # a signed 32-bit accumulator half never overflows: terms of at most qmax + 1 units
+    assert n_pix * (b["splat_qmax"] + 1) <= 2 ** 31 - 1
     n_vox = voxels_per_cell(g, views)
     assert b["cone_max_terms"] >= n_vox, (b["cone_max_terms"], n_vox)
     if name != "shallow":   # a grazing slab: the slice bound's bounding box is 22x the count there
         assert b["cone_max_terms"] <= 2 * n_vox, (b["cone_max_terms"], n_vox)
-    assert n_vox * (b["cone_qmax"] + 0.5) < 2 ** 31
+    assert n_vox * (b["cone_qmax"] + 1) <= 2 ** 31 - 1
     assert tile_window_need(g, b["interp_tile"]) <= b["interp_window"] - 1
     assert b["interp_local"] == (b["interp_window"] > 160)
     if b["bp_stage"] > 0:
