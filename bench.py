@@ -390,6 +390,37 @@ def c3_line(P, synth, args):
     return out
 
 
+def shard_line(P, grid, views, g, target, args, n_gpus=8):
+    """One GPU's share of a view-sharded C2 step: every n_gpus-th view (62 of 496)
+    into the full 256^3 volume, the same forward+backward step timed as is.  A
+    sharded step would sum the partial volumes with one all-reduce before the ReLU
+    and the loss; that exchange is not run here (one GPU), only modelled."""
+    import torch
+    idx = list(range(0, len(views), n_gpus))
+    sub = views.subset(idx)
+    plan = P.Plan(grid, sub)
+    knobs = plan.autotune() if not args.no_autotune else {"knobs": plan.knobs()}
+    gs = g[idx].contiguous()
+    tr = Trainer(P, plan, gs, target, torch.float32)
+    ms, kern = time_eager([tr], args.steps, args.warmup, per_stage=True)
+    nvox = grid.nx * grid.ny * grid.nz
+    vol_bytes = 4 * nvox
+    # ring all-reduce over n_gpus: each GPU sends and receives 2 (n-1)/n of the volume
+    # over its busiest link (about 153 GB/s per xGMI link)
+    ring_ms = 2 * (n_gpus - 1) / n_gpus * vol_bytes / 153e9 * 1e3
+    out = {"workload": "one GPU's share of C2 sharded by view over %d GPUs: every %dth view (%d of %d), full 256^3 "
+                       "volume, forward+backward w.r.t. M + Adam step, FP32 storage" % (n_gpus, n_gpus, len(idx), len(views)),
+           "views": len(idx), "knobs": knobs["knobs"], "ms_per_step": round(ms, 3),
+           "value": nvox * len(idx) / (ms * 1e-3),
+           "kernels_ms": {k: round(v, 3) for k, v in kern.items()},
+           "allreduce_model": {"bytes": vol_bytes, "single_ring_ms": round(ring_ms, 3),
+                               "note": "modelled, not measured: one ring over one xGMI link per GPU"}}
+    log("one GPU's view share (%d views): %.2f ms/step" % (len(idx), ms), json.dumps(out["kernels_ms"]))
+    del tr
+    torch.cuda.empty_cache()
+    return out
+
+
 def c5_line(P, synth, args):
     """The full C-arm scale workload (C5: 512^3 at 0.25 mm, 976^2 detector at
     0.308 mm, Radon 720 x 1381, 496-view sinusoid): the training step with FP16
@@ -533,6 +564,7 @@ def main():
                     help="largest number of oracle worker processes (one per usable core up to this)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 8-scan measurement")
     ap.add_argument("--no-c3", action="store_true", help="skip the circle-plus-arc (C3) line")
+    ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU view-share (62 of 496 views) line")
     ap.add_argument("--no-c5", action="store_true", help="skip the full C-arm scale (C5) line")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the forward reconstruction of the paper's own workload")
@@ -706,6 +738,8 @@ def main():
     if graph_ms is not None:
         out["bf16_graph"] = {"value": nvox * V / (graph_ms * 1e-3), "ms_per_step": round(graph_ms, 3),
                              "speedup_vs_f32": round(r["ms"] / graph_ms, 3) if main_store == "f32" else None}
+    if not args.no_shard:
+        out["view_shard"] = shard_line(P, grid, views, g, target, args)
     if not args.no_c3:
         out["c3"] = c3_line(P, synth, args)
         torch.cuda.empty_cache()

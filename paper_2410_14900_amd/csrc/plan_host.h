@@ -36,8 +36,8 @@ dc_status check_shape(const KernelShape& ks, std::string* err);
 enum ConeForm : char { kConeGeneral = 0, kConeQuadratic = 1, kConeZinv = 2 };
 
 // Largest number of voxel centres the cone adjoint may add into one accumulator
-// (one detector cell in one view); its fixed-point quantum is 2^30 / this of the
-// largest term, so beyond it the adjoint would lose float32 accuracy.
+// (one detector cell in one view); its fixed-point quantum is about 2^-31 times
+// this of the largest term, so beyond it the adjoint would lose float32 accuracy.
 static constexpr int kMaxCellTerms = 1 << 18;
 // Widest detector-BP window (intervals of one angle's sinogram row staged in LDS).
 static constexpr int kMaxInterpWindow = 512;
