@@ -110,8 +110,8 @@ dc_status dc_plan_create(const dc_grid* grid, const dc_view* views, int32_t n_vi
  * Per-view arrays (g, R, M, H, gF and their gradients) hold all samples' views
  * back to back; volumes (f, Gf, f_relu) hold one [nz][ny][nx] block per sample,
  * in sample order, so every stage call serves all samples with one launch per
- * kernel (the cone stages: one per run of consecutive samples that take the same
- * evaluation form, see dc_cone_bp).  A view range [v0, v0+nv) may span samples: dc_cone_bp writes the
+ * kernel (the cone stages too: over scans of different evaluation forms each
+ * workgroup takes its scan's own form).  A view range [v0, v0+nv) may span samples: dc_cone_bp writes the
  * volumes of the samples it meets (for nv = 0, the sample holding view v0, the
  * last one when v0 = n_views) and leaves the others untouched; dc_cone_bp_adjoint
  * reads each view's own sample volume.  dc_plan_create is n_samples = 1. */
@@ -186,12 +186,13 @@ typedef struct {
   int32_t interp_window;     /* detector-BP window: sinogram intervals staged per angle and pixel tile */
   int32_t interp_local;      /* 1 if that window takes the fixed-point position tap form (wide windows) */
   int32_t cone_max_terms;    /* bound on the voxel centres projecting into one detector cell of one view */
-  int32_t bp_stage;          /* detector pixels each cone-BP thread stages per view (0: taps from memory) */
+  int32_t bp_stage;          /* footprint rows each cone-BP thread stages per view (0: taps from memory) */
   int32_t cone_form;         /* 0: reciprocal per voxel, 1: 1/U quadratic in z, 2: z-invariant columns */
   int32_t bp_block[3];       /* cone-BP voxel block (x, y, z) */
   int32_t interp_tile[2];    /* detector-BP pixel tile (u, v) */
   float   splat_qmax;        /* units of the largest splat term */
   float   cone_qmax;         /* units of the largest cone-FP term */
+  int32_t bp_pitch;          /* pixels between the cone BP's staged footprint rows: 64 or 128 (0: taps from memory) */
 } dc_bounds;
 dc_status dc_plan_bounds(const dc_grid* grid, const dc_view* views, int32_t n_views, dc_bounds* out);
 /* Thread-local text of the last error (empty string if none). */

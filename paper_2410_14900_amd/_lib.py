@@ -51,7 +51,8 @@ class DcBounds(ctypes.Structure):
     _fields_ = [("splat_angles", c_int32), ("splat_max_terms", c_int32), ("splat_checked", c_int32),
                 ("interp_window", c_int32), ("interp_local", c_int32), ("cone_max_terms", c_int32),
                 ("bp_stage", c_int32), ("cone_form", c_int32), ("bp_block", c_int32 * 3),
-                ("interp_tile", c_int32 * 2), ("splat_qmax", c_float), ("cone_qmax", c_float)]
+                ("interp_tile", c_int32 * 2), ("splat_qmax", c_float), ("cone_qmax", c_float),
+                ("bp_pitch", c_int32)]
 
 
 class DcError(RuntimeError):

@@ -134,6 +134,7 @@ static dc_status upload_tables(Plan* p, const dc_view* views, const KernelShape&
   p->n_chunks = hp.n_chunks;
   p->cone_max_terms = hp.cone_max_terms;
   p->bp_stage = hp.bp_stage;
+  p->bp_pitch = hp.bp_pitch;
   p->cone_form = hp.cone_form;
   p->splat_qmax = fixed_point_qmax(hp.splat_max_terms);
   p->cone_qmax = fixed_point_qmax(hp.cone_max_terms);
@@ -271,6 +272,7 @@ dc_status dc_plan_bounds(const dc_grid* grid, const dc_view* views, int32_t n_vi
   b.interp_local = hp.interp_wl > kInterpLocalAbove ? 1 : 0;
   b.cone_max_terms = hp.cone_max_terms;
   b.bp_stage = hp.bp_stage;
+  b.bp_pitch = hp.bp_pitch;
   b.cone_form = hp.cone_form[0];
   b.splat_qmax = fixed_point_qmax(hp.splat_max_terms);
   b.cone_qmax = fixed_point_qmax(hp.cone_max_terms);

@@ -194,12 +194,14 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
   return b;
 }
 
-// STAGE = staged pixels per thread and view (the plan picks the smallest that
-// holds the largest footprint); STAGE == 0 selects direct global taps.  FORM
+// STAGE = staged footprint rows per thread and view and PITCH = pixels between
+// staged rows (64 or 128): the plan picks the smallest pitch that holds the widest
+// footprint and the smallest STAGE whose STAGE x (threads / PITCH) rows hold the
+// tallest.  STAGE == 0 selects direct global taps.  FORM
 // (staged form only) is the plan's choice for the sample (ConeForm), or
 // kConeMixed: a launch over samples of different forms reads each workgroup's
 // form from `forms` (one entry per sample).
-template <typename T, int STAGE, int FORM, int BY>
+template <typename T, int STAGE, int PITCH, int FORM, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
                                                  int nv, const int* __restrict__ first, int s_lo, int nzb,
@@ -247,29 +249,35 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
     // raw storage values: converted to float32 only when written to LDS, so
     // no use of a load comes before the interpolation of the current view
     T stg[STAGE > 0 ? STAGE : 1];
-    // fetch view v's footprint into registers (zero outside the detector and past
-    // the box).  The loads go through a resource spanning the view's image; a
-    // pixel off the detector takes an offset past its end, which reads 0, so no
-    // load sits behind a branch.
+    // fetch view v's footprint into registers: staged row r of the box (detector
+    // row j_lo + r) sits at tile[r * PITCH + c], and PITCH / 64 whole waves stage
+    // one row, kBPThreads / PITCH rows per pass, so a wave's row is uniform and
+    // its address arithmetic scalar.  The loads go through a resource spanning the
+    // view's image: a pixel left or right of the detector takes an offset past the
+    // resource's end, and so does every pixel of a row above or below it (a
+    // negative offset wraps above 2^31, past the image's bytes), which reads 0, so
+    // no load sits behind a branch.  Rows and columns past the box are staged too
+    // and never read.
     const unsigned img_bytes = (unsigned)(npix * sizeof(T));   // < 2^31: the plan caps nu nv at 2^31 / 4
+    constexpr int kRowsPerPass = STAGE > 0 ? kBPThreads / PITCH : 1;
+    const int scol = tid & (PITCH - 1);
+    const int srow = __builtin_amdgcn_readfirstlane(tid / PITCH);
     auto load_stage = [&](int v, const Box& b) {
       const __amdgpu_buffer_rsrc_t im =
           __builtin_amdgcn_make_buffer_rsrc((void*)(gF + (size_t)v * npix), (short)0, (int)img_bytes, kBufferWord3);
-      // row = floor((e + 1/2) / w): the quotient lies at least 1/(2w) from an
-      // integer, while the hardware reciprocal's error stays below 2e-3/w for e < 8192
-      const float rw = __builtin_amdgcn_rcpf((float)b.w);
-      const int n = b.w * b.h;
+      const int i_lo = __builtin_amdgcn_readfirstlane(b.i_lo), j_lo = __builtin_amdgcn_readfirstlane(b.j_lo);
+      const bool in = (unsigned)(i_lo + scol) < (unsigned)g.nu;
+      const unsigned cb = (unsigned)scol * (unsigned)sizeof(T);
 #pragma unroll
       for (int s = 0; s < STAGE; ++s) {
-        const int e = tid + kBPThreads * s;
-        const int row = (int)(((float)e + 0.5f) * rw);
-        const int ii = b.i_lo + (e - __mul24(row, b.w)), jj = b.j_lo + row;
-        const bool in = e < n && (unsigned)ii < (unsigned)g.nu && (unsigned)jj < (unsigned)g.nv;
-        buffer_load_raw(im, in ? (unsigned)(__mul24(jj, g.nu) + ii) * (unsigned)sizeof(T) : img_bytes, stg[s]);
+        const int jj = j_lo + srow + s * kRowsPerPass;
+        const unsigned off = (unsigned)(jj * g.nu + i_lo) * (unsigned)sizeof(T) + cb;
+        buffer_load_raw(im, in ? off : img_bytes, stg[s]);
       }
     };
-    // the whole slot is written (zeros past the box): nothing reads this buffer
-    // until the barrier that ends the current view
+    // element s of thread tid is staged row srow + s kRowsPerPass, column scol:
+    // tile index tid + kBPThreads s.  Nothing reads this buffer until the barrier
+    // that ends the current view
     auto store_stage = [&](int buf) {
 #pragma unroll
       for (int s = 0; s < STAGE; ++s) tile[buf][tid + kBPThreads * s] = to_f32(stg[s]);
@@ -313,8 +321,9 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
       const float* t = tile[buf];
       // Tap indices of voxels inside the volume need no clamping: every voxel of the
       // block's box [bx0, bx1] x [by0, by1] x [bz0, bz1] projects inside the convex
-      // hull of its corners' projections, and the staged box extends that hull by
-      // at least one pixel on each side (float rounding of the corners and of the
+      // hull of its corners' projections, and the box (at most PITCH wide and
+      // STAGE kRowsPerPass tall, by the plan) extends that hull by at least one
+      // pixel on each side (float rounding of the corners and of the
       // per-voxel walk is below 1e-4 pixel).  Padding lanes and slices (ix > bx1,
       // iy > by1 or iz > bz1 when a volume side is not a multiple of the block)
       // form taps from points outside that box, sometimes behind the source
@@ -332,8 +341,8 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
           const float wm = z == 0 ? c.w0m : fmaf((float)z, c.dw, c.w0m);
           const float yw = wm + kRoundMagic;
           const float fw = (wm - (yw - kRoundMagic)) + 0.5f;
-          const float* r0 = tc + __umul24(__float_as_uint(yw) - jbias, (unsigned)cur.w);
-          const float a00 = r0[0], a01 = r0[1], a10 = r0[cur.w], a11 = r0[cur.w + 1];
+          const float* r0 = tc + (__float_as_uint(yw) - jbias) * PITCH;
+          const float a00 = r0[0], a01 = r0[1], a10 = r0[PITCH], a11 = r0[PITCH + 1];
           const float top = fmaf(c.fu, a01 - a00, a00), bot = fmaf(c.fu, a11 - a10, a10);
           acc[z] = fmaf(c.r2, fmaf(fw, bot - top, top), acc[z]);
           if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -364,8 +373,8 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
           const float fu = fmaf(nu, r, kRoundMagic - yu) + 0.5f, fw = fmaf(nw, r, kRoundMagic - yw) + 0.5f;
           const int i = oi + (int)(__float_as_uint(yu) - kRoundMagicBits);
           const int j = oj + (int)(__float_as_uint(yw) - kRoundMagicBits);
-          const int q = __mul24(j, cur.w) + i;
-          const float a00 = t[q], a01 = t[q + 1], a10 = t[q + cur.w], a11 = t[q + cur.w + 1];
+          const int q = j * PITCH + i;
+          const float a00 = t[q], a01 = t[q + 1], a10 = t[q + PITCH], a11 = t[q + PITCH + 1];
           const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
           acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
           // keep the scheduler from hoisting every voxel's LDS reads at once
@@ -856,28 +865,37 @@ static hipError_t launch_cone_bp_run(const Plan& p, const void* gF, dc_dtype tF,
   dim3 grid((p.kg.nx + kBX - 1) / kBX, (p.kg.ny + BYr - 1) / BYr, nzb * (s_hi - s_lo + 1));
   return by_dtype(tF, [&](auto t) {
     using T = decltype(t);
-#define DC_BP1(ST, Z, BY)                                                                                           \
-  hipLaunchKernelGGL((k_cone_bp<T, ST, Z, BY>), grid, dim3(kBX, BY), 0, s, (const T*)gF, f, p.kg, p.d_proj, acc, \
-                     relu, v0, nv, p.d_first, s_lo, nzb, p.d_form)
-#define DC_BP(ST, Z)                   \
-  do {                                 \
-    if (BYr == 16) DC_BP1(ST, Z, 16);  \
-    else DC_BP1(ST, Z, 32);            \
+#define DC_BP1(ST, PI, Z, BY)                                                                                    \
+  hipLaunchKernelGGL((k_cone_bp<T, ST, PI, Z, BY>), grid, dim3(kBX, BY), 0, s, (const T*)gF, f, p.kg, p.d_proj,  \
+                     acc, relu, v0, nv, p.d_first, s_lo, nzb, p.d_form)
+#define DC_BP(ST, PI, Z)                   \
+  do {                                     \
+    if (BYr == 16) DC_BP1(ST, PI, Z, 16);  \
+    else DC_BP1(ST, PI, Z, 32);            \
   } while (0)
-#define DC_BP_FORMS(ST)                                            \
+#define DC_BP_FORMS(ST, PI)                                        \
   switch (form) {                                                  \
-    case kConeZinv: DC_BP(ST, kConeZinv); break;                   \
-    case kConeQuadratic: DC_BP(ST, kConeQuadratic); break;         \
-    case kConeMixed: DC_BP(ST, kConeMixed); break;                 \
-    default: DC_BP(ST, kConeGeneral); break;                       \
+    case kConeZinv: DC_BP(ST, PI, kConeZinv); break;               \
+    case kConeQuadratic: DC_BP(ST, PI, kConeQuadratic); break;     \
+    case kConeMixed: DC_BP(ST, PI, kConeMixed); break;             \
+    default: DC_BP(ST, PI, kConeGeneral); break;                   \
   }
-    switch (p.bp_stage) {
-      case 4: DC_BP_FORMS(4); break;
-      case 8: DC_BP_FORMS(8); break;
-      case 12: DC_BP_FORMS(12); break;
-      case 16: DC_BP_FORMS(16); break;
-      default: DC_BP(0, kConeGeneral); break;
+#define DC_BP_PITCH(ST)                                 \
+  do {                                                  \
+    if (p.bp_pitch == 64) {                             \
+      DC_BP_FORMS(ST, 64);                              \
+    } else {                                            \
+      DC_BP_FORMS(ST, 128);                             \
+    }                                                   \
+  } while (0)
+    switch (p.bp_pitch == 64 || p.bp_pitch == 128 ? p.bp_stage : 0) {
+      case 4: DC_BP_PITCH(4); break;
+      case 8: DC_BP_PITCH(8); break;
+      case 12: DC_BP_PITCH(12); break;
+      case 16: DC_BP_PITCH(16); break;
+      default: DC_BP(0, 64, kConeGeneral); break;
     }
+#undef DC_BP_PITCH
 #undef DC_BP_FORMS
 #undef DC_BP
 #undef DC_BP1

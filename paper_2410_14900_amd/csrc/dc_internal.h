@@ -73,7 +73,8 @@ struct Plan {
   double* d_proj = nullptr;      // [V][12]
   float* d_rmax2 = nullptr;      // [V] upper bound of (D/U)^2 over the volume
   int cone_max_terms = 0;        // max voxels sharing one (pixel cell) index in one view
-  int bp_stage = 0;              // staged pixels per thread in the backprojection (0: global taps)
+  int bp_stage = 0;              // staged rows per thread and view in the backprojection (0: global taps)
+  int bp_pitch = 0;              // pixels between the staged rows (64 or 128)
   // splat (Radon) work list: angle chunks that stay on one side of the diagonal
   int4* d_chunks = nullptr;      // (k0, count, column_major, 0)
   // samples (scans) of a batched plan: views of sample s are [first[s], first[s+1]);

@@ -254,12 +254,13 @@ dc_status plan_tables(const dc_grid* g, const dc_view* views, int n, const int* 
                     " voxel centres can project into one detector cell (limit " + std::to_string(kMaxCellTerms) +
                     "); the detector is too coarse for the voxel grid");
   p->cone_max_terms = (int)std::max(1.0, max_cell_terms);
-  // largest backprojection block footprint (same box rule as the kernel) ->
-  // how many pixels each of the backprojection's threads stages per view
+  // widest and tallest backprojection block footprint (same box rule as the kernel)
+  // -> the row pitch of the staged footprint and how many of its rows each thread
+  // stages per view
   {
     const int B[3] = {ks.bp_bx, ks.bp_by, ks.bp_bz};
     const int nb[3] = {(g->nx + B[0] - 1) / B[0], (g->ny + B[1] - 1) / B[1], (g->nz + B[2] - 1) / B[2]};
-    double worst = 0;
+    double worst_w = 0, worst_h = 0;
     for (int v = 0; v < n; ++v) {
       const double* P = &p->proj[12 * v];
       for (int bz = 0; bz < nb[2]; ++bz)
@@ -281,11 +282,19 @@ dc_status plan_tables(const dc_grid* g, const dc_view* views, int n, const int* 
             }
             // kernel box: [floor(min)-1, floor(max)+2], plus slack for float rounding
             const double bw = std::floor(imax) - std::floor(imin) + 5, bh = std::floor(jmax) - std::floor(jmin) + 5;
-            worst = std::max(worst, bw * bh);
+            worst_w = std::max(worst_w, bw);
+            worst_h = std::max(worst_h, bh);
           }
     }
-    const int need = (int)std::ceil(worst / (double)ks.bp_threads());
-    p->bp_stage = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 0;
+    // rows are staged PITCH pixels apart, each by PITCH / 64 whole waves, so a wave's
+    // row index is uniform; kBPThreads / PITCH rows per pass, STAGE passes
+    p->bp_pitch = worst_w <= 64 ? 64 : worst_w <= 128 ? 128 : 0;
+    p->bp_stage = 0;
+    if (p->bp_pitch > 0) {
+      const int need = (int)std::ceil(worst_h / (double)(ks.bp_threads() / p->bp_pitch));
+      p->bp_stage = need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : need <= 16 ? 16 : 0;
+    }
+    if (p->bp_stage == 0) p->bp_pitch = 0;
   }
   // Form of the cone kernels, decided per sample (so a batched plan computes what
   // each scan's own plan does).  den = U/D and num_u free of z on every view: a

@@ -72,7 +72,8 @@ struct HostPlan {
   int splat_checked = 1;         // 1: some pixel may land outside bins [-1, n_s)
   int interp_wl = 0;             // detector-BP window length
   int cone_max_terms = 0;        // bound on voxel centres per detector cell in one view
-  int bp_stage = 0;              // staged pixels per cone-BP thread (0: direct taps)
+  int bp_stage = 0;              // staged rows per cone-BP thread and view (0: direct taps)
+  int bp_pitch = 0;              // pixels between staged rows: 64 or 128 (0: direct taps)
 };
 
 // Geometry check of dc_validate; on failure *err holds the message.

@@ -44,10 +44,10 @@ int main(int argc, char** argv) {
   for (double x : hp.ang) ang_sum += x;
   std::printf(
       "{\"status\": 0, \"splat_angles\": %d, \"splat_max_terms\": %d, \"splat_checked\": %d, "
-      "\"interp_window\": %d, \"cone_max_terms\": %d, \"bp_stage\": %d, \"cone_form\": %d, "
+      "\"interp_window\": %d, \"cone_max_terms\": %d, \"bp_stage\": %d, \"bp_pitch\": %d, \"cone_form\": %d, "
       "\"n_chunks\": %d, \"splat_qmax\": %.9g, \"cone_qmax\": %.9g, \"proj_sum\": %.17g, \"ang_sum\": %.17g}\n",
       hp.splat_kc, hp.splat_max_terms, hp.splat_checked, hp.interp_wl, hp.cone_max_terms, hp.bp_stage,
-      (int)hp.cone_form[0], hp.n_chunks, (double)dc::fixed_point_qmax(hp.splat_max_terms),
+      hp.bp_pitch, (int)hp.cone_form[0], hp.n_chunks, (double)dc::fixed_point_qmax(hp.splat_max_terms),
       (double)dc::fixed_point_qmax(hp.cone_max_terms), proj_sum, ang_sum);
   return 0;
 }

@@ -6,8 +6,9 @@ The fixed-point stages rely on three bounds the plan derives in float64:
     (a 32-bit half of the splat's accumulator holds that many terms);
   * cone_max_terms: voxel centres projecting into one detector cell of one view
     (the same for the cone FP's accumulators);
-  * bp_stage: the cone BP stages each voxel block's detector footprint in LDS,
-    so the footprint of every block must fit the staged pixels;
+  * bp_pitch, bp_stage: the cone BP stages each voxel block's detector footprint
+    in LDS as rows bp_pitch pixels apart, so every block's footprint must be at
+    most bp_pitch wide and fit the staged rows;
 plus the detector BP's window, which must hold every bin interval a pixel tile
 touches on one angle.  Each is compared here with counts over every pixel,
 voxel, block and tile of the geometry.
@@ -126,12 +127,13 @@ def voxels_per_cell(g, views):
 
 
 def block_tap_extent(g, views, block):
-    """Largest (width + 2) x (height + 2) of the detector pixels the bilinear taps of
-    one cone-BP voxel block reach on one view (one pixel of margin each side)."""
+    """Largest width + 2 and largest height + 2 of the detector pixels the bilinear
+    taps of one cone-BP voxel block reach on one view (one pixel of margin each
+    side), each maximised over all blocks and views."""
     bx, by, bz = block
     rows = by * max(1, 2 ** 21 // (by * g.nx * bz))        # about 2M voxels per chunk
     nxp = -(-g.nx // bx) * bx
-    worst = 0
+    worst_w = worst_h = 0
     for v in range(len(views)):
         one = views.subset([v])
         for z0 in range(0, g.nz, bz):
@@ -148,8 +150,9 @@ def block_tap_extent(g, views, block):
                     a = np.pad(a, ((0, bz - len(z)), (0, nyp - len(y)), (0, nxp - g.nx)), constant_values=np.nan)
                     a = a.reshape(bz, nyp // by, by, nxp // bx, bx)
                     ext.append(np.nanmax(a, axis=(0, 2, 4)) - np.nanmin(a, axis=(0, 2, 4)) + 2)
-                worst = max(worst, int(np.nanmax((ext[0] + 2) * (ext[1] + 2))))
-    return worst
+                worst_w = max(worst_w, int(np.nanmax(ext[0])) + 2)
+                worst_h = max(worst_h, int(np.nanmax(ext[1])) + 2)
+    return worst_w, worst_h
 
 
 def tile_window_need(g, tile):
@@ -190,9 +193,13 @@ def test_plan_bounds_hold_against_brute_force_counts(P, name):
     assert n_vox * (b["cone_qmax"] + 1) <= 2 ** 31 - 1
     assert tile_window_need(g, b["interp_tile"]) <= b["interp_window"] - 1
     assert b["interp_local"] == (b["interp_window"] > 160)
+    assert (b["bp_pitch"] in (64, 128)) == (b["bp_stage"] > 0)
     if b["bp_stage"] > 0:
+        # rows bp_pitch pixels apart, threads / bp_pitch rows per pass, bp_stage passes
         threads = b["bp_block"][0] * b["bp_block"][1]
-        assert block_tap_extent(g, views, b["bp_block"]) <= b["bp_stage"] * threads
+        w, h = block_tap_extent(g, views, b["bp_block"])
+        assert w <= b["bp_pitch"], (w, b["bp_pitch"])
+        assert h <= b["bp_stage"] * threads // b["bp_pitch"], (h, b["bp_stage"], b["bp_pitch"])
     print(name, {k: b[k] for k in ("splat_max_terms", "cone_max_terms", "bp_stage", "interp_window")},
           "brute:", n_pix, n_vox)
 
@@ -287,5 +294,5 @@ def test_host_plan_code_under_address_and_undefined_sanitizers(P, sanitized_driv
         assert got["status"] == st, (name, got, st)
         if st == 0:
             for k in ("splat_angles", "splat_max_terms", "splat_checked", "interp_window", "cone_max_terms",
-                      "bp_stage", "cone_form", "splat_qmax", "cone_qmax"):
+                      "bp_stage", "bp_pitch", "cone_form", "splat_qmax", "cone_qmax"):
                 assert got[k] == b[k], (name, k, got[k], b[k])
