@@ -207,7 +207,11 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
                                                  int nv, const int* __restrict__ first, int s_lo, int nzb,
                                                  const int* __restrict__ forms) {
   constexpr int kBPThreads = kBX * BY;
-  constexpr int kTile = STAGE > 0 ? kBPThreads * STAGE : 1;
+  // staged rows lie kLP floats apart in LDS: 8 past the row's pixels, so a pixel and the
+  // one below it fall in different banks (with rows exactly 64 or 128 floats apart they
+  // share one, and lanes on neighbouring rows conflicted at 2.8 cycles per read)
+  constexpr int kLP = PITCH + 8;
+  constexpr int kTile = STAGE > 0 ? STAGE * (kBPThreads / PITCH) * kLP : 1;
   __shared__ float tile[2][kTile];
   const int tid = threadIdx.y * kBX + threadIdx.x;
   // grid z = (sample, z-block): this workgroup sums the views of its sample that
@@ -250,7 +254,7 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
     // no use of a load comes before the interpolation of the current view
     T stg[STAGE > 0 ? STAGE : 1];
     // fetch view v's footprint into registers: staged row r of the box (detector
-    // row j_lo + r) sits at tile[r * PITCH + c], and PITCH / 64 whole waves stage
+    // row j_lo + r) sits at tile[r * kLP + c], and PITCH / 64 whole waves stage
     // one row, kBPThreads / PITCH rows per pass, so a wave's row is uniform and
     // its address arithmetic scalar.  The loads go through a resource spanning the
     // view's image: a pixel left or right of the detector takes an offset past the
@@ -275,12 +279,11 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
         buffer_load_raw(im, in ? off : img_bytes, stg[s]);
       }
     };
-    // element s of thread tid is staged row srow + s kRowsPerPass, column scol:
-    // tile index tid + kBPThreads s.  Nothing reads this buffer until the barrier
-    // that ends the current view
+    // element s of thread tid is staged row srow + s kRowsPerPass, column scol.
+    // Nothing reads this buffer until the barrier that ends the current view
     auto store_stage = [&](int buf) {
 #pragma unroll
-      for (int s = 0; s < STAGE; ++s) tile[buf][tid + kBPThreads * s] = to_f32(stg[s]);
+      for (int s = 0; s < STAGE; ++s) tile[buf][(srow + s * kRowsPerPass) * kLP + scol] = to_f32(stg[s]);
     };
     // Footprints are computed by one wave per view, two views ahead, and passed
     // on in a two-slot LDS ring: the box of view v sits in slot (v - v0) & 1 from
@@ -341,8 +344,8 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
           const float wm = z == 0 ? c.w0m : fmaf((float)z, c.dw, c.w0m);
           const float yw = wm + kRoundMagic;
           const float fw = (wm - (yw - kRoundMagic)) + 0.5f;
-          const float* r0 = tc + (__float_as_uint(yw) - jbias) * PITCH;
-          const float a00 = r0[0], a01 = r0[1], a10 = r0[PITCH], a11 = r0[PITCH + 1];
+          const float* r0 = tc + (__float_as_uint(yw) - jbias) * kLP;
+          const float a00 = r0[0], a01 = r0[1], a10 = r0[kLP], a11 = r0[kLP + 1];
           const float top = fmaf(c.fu, a01 - a00, a00), bot = fmaf(c.fu, a11 - a10, a10);
           acc[z] = fmaf(c.r2, fmaf(fw, bot - top, top), acc[z]);
           if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -373,8 +376,8 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
           const float fu = fmaf(nu, r, kRoundMagic - yu) + 0.5f, fw = fmaf(nw, r, kRoundMagic - yw) + 0.5f;
           const int i = oi + (int)(__float_as_uint(yu) - kRoundMagicBits);
           const int j = oj + (int)(__float_as_uint(yw) - kRoundMagicBits);
-          const int q = j * PITCH + i;
-          const float a00 = t[q], a01 = t[q + 1], a10 = t[q + PITCH], a11 = t[q + PITCH + 1];
+          const int q = j * kLP + i;
+          const float a00 = t[q], a01 = t[q + 1], a10 = t[q + kLP], a11 = t[q + kLP + 1];
           const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
           acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
           // keep the scheduler from hoisting every voxel's LDS reads at once
