@@ -41,7 +41,24 @@ hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s) {
 
 // max |w x| over each view, as float bits (non-negative floats order like their bits),
 // into vmax[v - v0] (zeroed before)
-template <typename Tin, bool WCOS>
+// four consecutive storage values as float32 (one 16- or 8-byte load)
+__device__ __forceinline__ void load4(const float* p, float x[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  x[0] = q.x; x[1] = q.y; x[2] = q.z; x[3] = q.w;
+}
+template <typename T>
+__device__ __forceinline__ void load4(const T* p, float x[4]) {
+  const uint2 q = *reinterpret_cast<const uint2*>(p);
+  T h[4];
+  __builtin_memcpy(h, &q, sizeof(q));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) x[k] = to_f32(h[k]);
+}
+
+// VEC: nu is a multiple of 4, so every row starts 16-byte (float) or 8-byte
+// (16-bit storage) aligned in the 16-byte aligned array, and a thread takes four
+// consecutive pixels of a row with one load
+template <typename Tin, bool WCOS, bool VEC>
 __global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img, unsigned* __restrict__ vmax, KGrid g,
                                                      const float4* __restrict__ viewf, int v0) {
   __shared__ float red[256];
@@ -50,16 +67,31 @@ __global__ __launch_bounds__(256) void k_view_absmax(const Tin* __restrict__ img
   const Tin* im = img + (size_t)v * npix;
   const float D = viewf[v].x;
   float mx = 0.f;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npix; q += gridDim.x * blockDim.x) {
-    float x = to_f32(im[q]);
-    if (WCOS) {
-      const int j = q / g.nu, i = q - j * g.nu;
-      const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
-      // hardware rsqrt: the argument is at least D^2, far from the denormal
-      // range that rsqrtf's scaling guards (the splat and its transpose use the same)
-      x *= D * __builtin_amdgcn_rsqf(fmaf(xu, xu, fmaf(yv, yv, D * D)));
+  // whole rows per workgroup (rows blockIdx.x, + gridDim.x, ...): coalesced loads
+  // and the pixel's row known without a division
+  for (int j = blockIdx.x; j < g.nv; j += gridDim.x) {
+    const Tin* row = im + (size_t)j * g.nu;
+    const float yv = (j - g.cv) * g.dv;
+    const float r2 = fmaf(yv, yv, D * D);
+    // hardware rsqrt: the argument is at least D^2, far from the denormal range
+    // that rsqrtf's scaling guards; the same weight as the splat's, bit for bit
+    auto weigh = [&](float x, int i) {
+      if (WCOS) {
+        const float xu = (i - g.cu) * g.du;
+        x *= D * __builtin_amdgcn_rsqf(fmaf(xu, xu, r2));
+      }
+      return fabsf(x);
+    };
+    if (VEC) {
+      for (int i = 4 * threadIdx.x; i < g.nu; i += 4 * blockDim.x) {
+        float x[4];
+        load4(row + i, x);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mx = fmaxf(mx, weigh(x[k], i + k));
+      }
+    } else {
+      for (int i = threadIdx.x; i < g.nu; i += blockDim.x) mx = fmaxf(mx, weigh(to_f32(row[i]), i));
     }
-    mx = fmaxf(mx, fabsf(x));
   }
   red[threadIdx.x] = mx;
   __syncthreads();
@@ -382,13 +414,17 @@ hipError_t launch_splat(const Plan& p, const void* img, dc_dtype t_in, bool wcos
   if (e != hipSuccess) return e;
   return by_dtype(t_in, [&](auto tin) {
     using Tin = decltype(tin);
-    const int mblocks = std::max(1, std::min(64, (p.kg.nu * p.kg.nv + 4095) / 4096));
-    if (wcos)
-      hipLaunchKernelGGL((k_view_absmax<Tin, true>), dim3(mblocks, nv), dim3(256), 0, s, (const Tin*)img,
-                         vmax, p.kg, (const float4*)p.d_view, v0);
-    else
-      hipLaunchKernelGGL((k_view_absmax<Tin, false>), dim3(mblocks, nv), dim3(256), 0, s, (const Tin*)img,
-                         vmax, p.kg, (const float4*)p.d_view, v0);
+    const int mblocks = std::max(1, std::min(64, p.kg.nv / 8));   // about 8 rows per workgroup
+#define DC_ABSMAX(W, VEC)                                                                                    \
+  hipLaunchKernelGGL((k_view_absmax<Tin, W, VEC>), dim3(mblocks, nv), dim3(256), 0, s, (const Tin*)img, vmax, \
+                     p.kg, (const float4*)p.d_view, v0)
+    const bool vec = p.kg.nu % 4 == 0;
+    if (wcos) {
+      if (vec) DC_ABSMAX(true, true); else DC_ABSMAX(true, false);
+    } else {
+      if (vec) DC_ABSMAX(false, true); else DC_ABSMAX(false, false);
+    }
+#undef DC_ABSMAX
     hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
     return by_dtype(t_out, [&](auto tout) {
