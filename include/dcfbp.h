@@ -245,8 +245,8 @@ dc_status dc_detector_bp_adjoint(dc_plan plan, const void* GgF, dc_dtype tF, voi
  * The plan evaluates each sample's projections (here and in dc_cone_bp_adjoint)
  * in one of three forms chosen from its geometry: per voxel column when no view's
  * depth U or detector u coordinate varies along z (detector v axis along z); with
- * 1/U taken along z as its quadratic Taylor polynomial about a segment's first
- * voxel when U changes by at most 2.5e-4 of itself per voxel step; with a
+ * 1/U taken along z as its quadratic Taylor polynomial about a segment's middle
+ * when U changes by at most 5e-4 of itself per voxel step; with a
  * reciprocal per voxel otherwise.  The forms agree to float32 rounding, and each
  * is deterministic. */
 dc_status dc_cone_bp(dc_plan plan, const void* gF, dc_dtype tF, float* f, int32_t accumulate,

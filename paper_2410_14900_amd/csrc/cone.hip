@@ -100,10 +100,10 @@ __device__ __forceinline__ ColumnMapZ column_map_z(const double* __restrict__ P,
 // the hardware reciprocal serves), so n rr = u - iu0 - 1/2 and likewise v, and
 // every coordinate is scaled by sf = 1/sqrt(S), so rr^2 = S (D/U)^2 carries the
 // fixed-point quantum.  den and the numerators at the segment start are formed in
-// float64 (where they cancel).  With FLOAT_STEPS (den changes by at most 2.5e-4
+// float64 (where they cancel).  With FLOAT_STEPS (den changes by at most 5e-4
 // of itself per voxel step) their z-steps are formed in float from the view's
 // scaled steps zd, zu, zv (dden, dnum_u, dnum_v): the product au zd is then at
-// most 2.5e-4 au den, so the step's error stays near one rounding of it;
+// most 5e-4 au den, so the step's error stays near one rounding of it;
 // otherwise they are formed in float64.
 struct ColumnMapF {
   float den, lu, lv;   // at the first voxel of the segment
@@ -356,17 +356,20 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
         const ColumnMapF c = column_map_fp<F == kConeQuadratic>(proj + 12 * v, ix, iy, iz0, 1.0f, zd,
                                                                 (float)proj[12 * v + 6], (float)proj[12 * v + 10]);
         const int oi = c.iu0 - cur.i_lo, oj = c.jv0 - cur.j_lo;
-        // kConeQuadratic (den moves by at most 2.5e-4 of itself per voxel step): 1/den
-        // along the column is its quadratic Taylor polynomial about the first voxel,
-        // whose remainder is below (7 x 2.5e-4)^3 of it, far below float rounding
-        float r0 = __builtin_amdgcn_rcpf(c.den);
-        r0 = fmaf(r0, fmaf(-c.den, r0, 1.0f), r0);
-        const float r1 = -r0 * r0 * zd, r2 = -r1 * r0 * zd;   // 1/den = r0 + r1 z + r2 z^2
+        // kConeQuadratic (den moves by at most 5e-4 of itself per voxel step): 1/den
+        // along the column is its quadratic Taylor polynomial about the column's middle
+        // zc, whose remainder is below (3.5 x 5e-4)^3 of it, far below float rounding
+        constexpr float zc = 0.5f * (kZC - 1);
+        const float dc = F == kConeQuadratic ? fmaf(zc, zd, c.den) : c.den;
+        float r0 = __builtin_amdgcn_rcpf(dc);
+        r0 = fmaf(r0, fmaf(-dc, r0, 1.0f), r0);
+        const float r1 = -r0 * r0 * zd, r2 = -r1 * r0 * zd;   // 1/den = r0 + r1 (z - zc) + r2 (z - zc)^2
 #pragma unroll
         for (int z = 0; z < kZC; ++z) {
-          const float r = z == 0 ? r0
-                          : F == kConeQuadratic ? fmaf((float)z, r1, fmaf((float)(z * z), r2, r0))
-                                                : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
+          const float tz = (float)z - zc;
+          const float r = F == kConeQuadratic ? fmaf(tz, r1, fmaf(tz * tz, r2, r0))
+                          : z == 0            ? r0
+                                              : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
           const float nu = z == 0 ? c.lu : fmaf((float)z, c.ldu, c.lu);
           const float nw = z == 0 ? c.lv : fmaf((float)z, c.ldv, c.lv);
           // one fused rounding with the 1.5 * 2^23 trick gives the cell floor(u) (an
@@ -525,9 +528,9 @@ __device__ __forceinline__ float pick(const float (&S)[kFV], int w) {
 // Gf: the z-bricked (masked) gradient written by k_vol_brick.
 // FORM (ConeForm) as in the backprojection; with kConeZinv each (segment, view)
 // has one u, one tap column and one weight, and a segment whose column misses
-// the tile is skipped whole.  With kConeQuadratic (den changes by at most 2.5e-4 of
+// the tile is skipped whole.  With kConeQuadratic (den changes by at most 5e-4 of
 // itself per voxel step) 1/den along the segment is its quadratic Taylor
-// polynomial about the first voxel: the remainder is below (15 x 2.5e-4)^3 =
+// polynomial about the segment's middle: the remainder is below (7.5 x 5e-4)^3 =
 // 5.3e-8 of it, float rounding, and every voxel's reciprocal is independent.
 template <typename Tout, int FORM, int TI>
 __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, Tout* __restrict__ GgF, KGrid g,
@@ -760,14 +763,19 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
         const float zd = pick(zstep_d, w);
         const ColumnMapF c = column_map_fp<F == kConeQuadratic>(proj + 12 * (va + w), ix, iy, iz0, pick(sinv, w), zd,
                                                                  pick(zstep_u, w), pick(zstep_v, w));
-        float rr0 = __builtin_amdgcn_rcpf(c.den);
-        rr0 = fmaf(rr0, fmaf(-c.den, rr0, 1.0f), rr0);   // one Newton step: a correctly rounded start
-        const float r1 = -rr0 * rr0 * zd, r2 = -r1 * rr0 * zd;   // 1/den = rr0 + r1 z + r2 z^2
+        // kConeQuadratic: 1/den along the segment is its quadratic Taylor polynomial
+        // about the segment's middle zc (remainder below (7.5 x 5e-4)^3 = 5.3e-8 of it)
+        constexpr float zc = 0.5f * (kFZS - 1);
+        const float dc = F == kConeQuadratic ? fmaf(zc, zd, c.den) : c.den;
+        float rr0 = __builtin_amdgcn_rcpf(dc);
+        rr0 = fmaf(rr0, fmaf(-dc, rr0, 1.0f), rr0);   // one Newton step: a correctly rounded start
+        const float r1 = -rr0 * rr0 * zd, r2 = -r1 * rr0 * zd;   // 1/den = rr0 + r1 (z - zc) + r2 (z - zc)^2
 #pragma unroll
         for (int z = 0; z < kFZS; ++z) {
-          const float rr = z == 0 ? rr0
-                           : F == kConeQuadratic ? fmaf((float)z, r1, fmaf((float)(z * z), r2, rr0))
-                                                 : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
+          const float tz = (float)z - zc;
+          const float rr = F == kConeQuadratic ? fmaf(tz, r1, fmaf(tz * tz, r2, rr0))
+                           : z == 0            ? rr0
+                                               : __builtin_amdgcn_rcpf(fmaf((float)z, zd, c.den));
           // nu rr = u - iu0 - 1/2 (and likewise v): one fused rounding with the
           // 1.5 * 2^23 trick gives the cell floor(u) (an exact integer u may give the
           // cell below with fraction 1: the same taps, and range checks as usual),

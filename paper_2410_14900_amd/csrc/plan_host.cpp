@@ -299,10 +299,10 @@ dc_status plan_tables(const dc_grid* g, const dc_view* views, int n, const int* 
   // Form of the cone kernels, decided per sample (so a batched plan computes what
   // each scan's own plan does).  den = U/D and num_u free of z on every view: a
   // voxel column keeps one u and one weight per view, formed once per column.
-  // Otherwise, if den changes by at most 2.5e-4 of itself per voxel step, 1/den
-  // along a 16-voxel segment is its quadratic Taylor polynomial about the first
-  // voxel, whose remainder is below (15 x 2.5e-4)^3 = 5.3e-8 (float rounding),
-  // and replaces the per-voxel reciprocal.
+  // Otherwise, if den changes by at most 5e-4 of itself per voxel step, 1/den
+  // along a 16-voxel segment is its quadratic Taylor polynomial about the
+  // segment's middle, whose remainder is below (7.5 x 5e-4)^3 = 5.3e-8 (float
+  // rounding), and replaces the per-voxel reciprocal.
   p->cone_form.assign(n_samples, kConeZinv);
   for (int smp = 0; smp < n_samples; ++smp) {
     bool zinv = true;
@@ -311,7 +311,7 @@ dc_status plan_tables(const dc_grid* g, const dc_view* views, int n, const int* 
       zinv = zinv && p->proj[12 * v + 2] == 0.0 && p->proj[12 * v + 6] == 0.0;
       worst = std::max(worst, zrel[v]);
     }
-    p->cone_form[smp] = zinv ? kConeZinv : worst <= 2.5e-4 ? kConeQuadratic : kConeGeneral;
+    p->cone_form[smp] = zinv ? kConeZinv : worst <= 5e-4 ? kConeQuadratic : kConeGeneral;
   }
   return DC_OK;
 }
