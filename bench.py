@@ -71,10 +71,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (6_831_928_144 + 693_006_984,
-                                 "e101a950a47d2cc5436bedd31394c3b03487a311663d9a411d76ae579242f5f0"),
-    ("weight_radon", "f32"): (1_044_191_127 + 518_986_373,
-                              "5acb0d4045fc0a1589a1fdc921cc0f1307fddb63dc3e62cf82613067bbc2b37f"),
+    ("cone_bp_adjoint", "f32"): (6_817_655_131 + 693_008_392,
+                                 "343edb291411f78a421eb3c6b6fc24b8bcbc3f3860d4a006500e52e1dcce26b6"),
+    ("weight_radon", "f32"): (1_044_769_137 + 518_986_432,
+                              "0dd99e62e381cf9e454098f4e4d14a2f91a4d59c07950c9982e6de8ca2b2f1fd"),
 }
 
 
