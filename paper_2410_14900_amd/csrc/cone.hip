@@ -427,11 +427,12 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
 // 4 views).  In voxel-index space these
 // are four half-spaces L_k(x) >= 0 (affine because the projection is
 // projective with a positive denominator).  The voxels are enumerated as
-// x-runs of 16-voxel z-segments: every (z-segment, y) row of the volume is
-// intersected with the four half-spaces (a conservative x-interval; the exact
-// test is made per voxel), the non-empty rows are compacted into an LDS list,
-// and a flattened index over the list gives every lane one (x, y, z-segment)
-// item, walked in z like the backprojection.
+// runs of 16-voxel z-segments along x or y (per view, across the rays): every
+// (z-segment, y) row of the volume (or (z-segment, x) row) is intersected with
+// the four half-spaces (a conservative interval along the run; the exact test is
+// made per voxel), the non-empty rows are compacted into an LDS list, and a
+// flattened index over the list gives every lane one (x, y, z-segment) item,
+// walked in z like the backprojection.
 //
 // A voxel with fractional projection (ib + fu, jb + fv) and weight g adds
 // g(1-fu)(1-fv), g fu(1-fv), g(1-fu)fv, g fu fv to its four taps.  With the
@@ -541,7 +542,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
                                                  const int* __restrict__ forms) {
   __shared__ double sL[kFV][4][4], sNegInvA[kFV][4];
   __shared__ int sRow[kFROWS], sXlo[kFROWS], sPre[kFROWS + 1];
-  __shared__ unsigned char sLay[kFROWS];   // z-layer of each listed row (sRow holds its y)
+  __shared__ unsigned char sLay[kFROWS];   // z-layer of each listed row (sRow holds its fixed coordinate)
   __shared__ int sScan[256];
   __shared__ int sCount, sNL;
   __shared__ unsigned char sLayerOn[kFMaxLayers];
@@ -569,6 +570,14 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
     grp -= ng;
   }
   if (nvw <= 0) return;
+  // Runs of voxels along y when the view's depth (den) changes faster along x than
+  // along y, along x otherwise: along the direction closer to the rays, consecutive
+  // voxels project into the same detector cell, and the lanes of one wave (which
+  // take consecutive voxels of a run) would add into that one LDS word together.
+  // Across the rays they spread over the tile's columns.  rc: the coordinate a run
+  // walks (0: x, 1: y); the other is the row's fixed coordinate.
+  const bool ym = fabs(proj[12 * va]) > fabs(proj[12 * va + 1]);
+  const int rc = ym ? 1 : 0;
   const int nzs = (g.nz + kFZS - 1) / kFZS;
   Gf += (size_t)smp * g.nx * g.ny * nzs * kFZS;
   const int ti = tile % tiles_u, tj = tile / tiles_u;
@@ -585,7 +594,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       else if (k == 2) val = nvv - (j0 - 1) * den;  // j* >= j0 - 1
       else val = j1 * den - nvv;                    // j* <  j1
       sL[w][k][c] = val;
-      if (c == 0) sNegInvA[w][k] = val != 0.0 ? -1.0 / val : 0.0;
+      if (c == rc) sNegInvA[w][k] = val != 0.0 ? -1.0 / val : 0.0;
     }
   }
   for (int q = threadIdx.x; q < kFV * kFW * kFH; q += blockDim.x) {
@@ -618,7 +627,8 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
     sNL = n;
   }
   __syncthreads();
-  const int nrows = sNL * g.ny;
+  const int nfix = ym ? g.nx : g.ny, nrun = ym ? g.ny : g.nx;
+  const int nrows = sNL * nfix;
   const float gabs = __uint_as_float(gmax_bits[smp]);
   // per view: the quantum S, 1/sqrt(S) (the general forms scale their
   // coordinates by it) and the scaled z-steps of den, num_u and num_v
@@ -637,20 +647,21 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
   for (int r0 = 0; r0 < nrows; r0 += kFROWS) {
     if (threadIdx.x == 0) sCount = 0;
     __syncthreads();
-    // 1. rows of this batch whose x-interval may meet one of the frusta
+    // 1. rows of this batch (layer and fixed coordinate) whose interval along the
+    // run coordinate may meet one of the frusta (written below for runs along x)
     for (int r = r0 + threadIdx.x; r < min(nrows, r0 + kFROWS); r += blockDim.x) {
-      const int li = r / g.ny, iy = r - li * g.ny;
+      const int li = r / nfix, fc = r - li * nfix;
       const int zs = sLayer[li];
       const double zlo = zs * kFZS, zhi = min(g.nz - 1, zs * kFZS + kFZS - 1);
       double ulo = 1e30, uhi = -1e30;
       for (int w = 0; w < nvw; ++w) {
-        double xlo = 0.0, xhi = g.nx - 1;
+        double xlo = 0.0, xhi = nrun - 1;
         bool empty = false;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const double* L = sL[w][k];
-          const double a = L[0];
-          const double c0 = fma(L[1], (double)iy, L[3]);
+          const double a = L[rc];
+          const double c0 = fma(L[1 - rc], (double)fc, L[3]);
           const double cm = fmax(fma(L[2], zlo, c0), fma(L[2], zhi, c0));
           // L_k = a x + cm >= -eta up to xb: eta = 0.01 in L's units (pixel x den)
           // keeps at least 0.01 pixel of slack (den <= 1) over the per-voxel float
@@ -667,7 +678,7 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       }
       if (ulo <= uhi) {
         const int slot = atomicAdd(&sCount, 1);
-        sRow[slot] = iy;
+        sRow[slot] = fc;
         sLay[slot] = (unsigned char)zs;
         sXlo[slot] = (int)ulo;
         sPre[slot] = (int)(uhi - ulo) + 1;   // length for now
@@ -715,8 +726,8 @@ __global__ __launch_bounds__(256) void k_cone_fp(const float* __restrict__ Gf, T
       } else {
         while (sPre[lo + 1] <= q) ++lo;       // sPre[cnt] = total ends the scan
       }
-      const int iy = sRow[lo];
-      const int ix = sXlo[lo] + (q - sPre[lo]);
+      const int fc = sRow[lo], rcoord = sXlo[lo] + (q - sPre[lo]);
+      const int iy = ym ? rcoord : fc, ix = ym ? fc : rcoord;
       const int zs = sLay[lo];
       const int iz0 = zs * kFZS;
       // the segment's brick: four 16-byte loads from one address (slices past the
