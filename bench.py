@@ -71,9 +71,9 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (6_817_655_131 + 693_008_392,
-                                 "343edb291411f78a421eb3c6b6fc24b8bcbc3f3860d4a006500e52e1dcce26b6"),
-    ("weight_radon", "f32"): (1_044_769_137 + 518_986_432,
+    ("cone_bp_adjoint", "f32"): (5_129_577_831 + 693_024_992,
+                                 "c46c2e0a1785198254f511e13fec00702a6410a3402ad2361347bc7427198e57"),
+    ("weight_radon", "f32"): (1_045_034_629 + 518_987_163,
                               "0dd99e62e381cf9e454098f4e4d14a2f91a4d59c07950c9982e6de8ca2b2f1fd"),
 }
 
