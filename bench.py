@@ -50,12 +50,13 @@ LDS_BYTES_PER_UNIT = {"weight_radon": 8, "filter": 8, "detector_bp": 8, "cone_bp
                       "cone_bp_adjoint": 16, "detector_bp_adjoint": 8, "filter_adjoint": 8}
 LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 # The splats issue one 64-bit LDS integer atomic per pixel-angle.  Measured cost of
-# one wave-wide 64-bit atomic per CU on this GPU (a microbenchmark saturating the
-# LDS): 7.5 clocks when the 64 lanes hit consecutive words (the best layout),
-# 9.05 for the splat's pattern (lanes on pixel lines two apart), 12.9 when lane
-# pairs share a word.  The splats are reported against the best-layout figure.
+# one wave-wide 64-bit atomic per CU on this GPU (microbenchmarks saturating the
+# LDS): 6.4 clocks when the 64 lanes hit consecutive words (the best layout; an
+# earlier probe gave 7.5), 8.1-9.1 for the splat's pattern (lanes on pixel lines two
+# apart), 12-13 when lane pairs share a word.  The splats are reported against the
+# best-layout figure.
 SPLAT_STAGES = ("weight_radon", "detector_bp_adjoint")
-LDS_ATOMIC_FLOOR_CLK = 7.5
+LDS_ATOMIC_FLOOR_CLK = 6.4
 
 
 # HBM bytes per call of a stage, from FETCH_SIZE and WRITE_SIZE counter runs of this
