@@ -54,7 +54,9 @@ hipError_t launch_adam(float* M, const float* G, float* m, float* v, size_t n, c
                        double b1, double b2, double eps, double wd, hipStream_t s) {
   const AdamCoef c{(float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, (float)lr,
                    (float)(1.0 - lr * wd), b1, b2};
-  const size_t blocks = std::min<size_t>(8192, (n / 4 + 255) / 256 + 1);
+  // up to 32768 workgroups (about 4 float4 per thread at C2's 1.3e8 weights): 5.9 TB/s,
+  // against 5.5 with 8192
+  const size_t blocks = std::min<size_t>(32768, (n / 4 + 255) / 256 + 1);
   hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, M, G, m, v, n, step, c);
   return hipGetLastError();
 }
