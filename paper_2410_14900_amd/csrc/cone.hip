@@ -194,6 +194,13 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
   return b;
 }
 
+// Staging classes and forms whose kernel is compiled for 6 waves per SIMD (three
+// 512-thread workgroups per CU): the quadratic and reciprocal forms with 4 or 8
+// staged rows per thread, the classes real geometries use (80 registers, a few
+// spilled; 7% faster on C2 than at 4 waves).  The others keep the default.
+template <int STAGE, int FORM>
+inline constexpr bool kBpSixWaves = (FORM == kConeQuadratic || FORM == kConeGeneral) && STAGE > 0 && STAGE <= 8;
+
 // STAGE = staged footprint rows per thread and view and PITCH = pixels between
 // staged rows (64 or 128): the plan picks the smallest pitch that holds the widest
 // footprint and the smallest STAGE whose STAGE x (threads / PITCH) rows hold the
@@ -202,7 +209,8 @@ __device__ __forceinline__ Box block_footprint(const double* __restrict__ P, int
 // kConeMixed: a launch over samples of different forms reads each workgroup's
 // form from `forms` (one entry per sample).
 template <typename T, int STAGE, int PITCH, int FORM, int BY>
-__global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
+__global__ __launch_bounds__(kBX * BY) __attribute__((amdgpu_waves_per_eu(kBpSixWaves<STAGE, FORM> ? 6 : 1)))
+void k_cone_bp(const T* __restrict__ gF, float* __restrict__ f, KGrid g,
                                                  const double* __restrict__ proj, int acc_in, int relu, int v0,
                                                  int nv, const int* __restrict__ first, int s_lo, int nzb,
                                                  const int* __restrict__ forms) {
@@ -383,9 +391,14 @@ __global__ __launch_bounds__(kBX * BY) void k_cone_bp(const T* __restrict__ gF, 
           const float a00 = t[q], a01 = t[q + 1], a10 = t[q + kLP], a11 = t[q + kLP + 1];
           const float top = fmaf(fu, a01 - a00, a00), bot = fmaf(fu, a11 - a10, a10);
           acc[z] = fmaf(r * r, fmaf(fw, bot - top, top), acc[z]);
-          // keep the scheduler from hoisting every voxel's LDS reads at once
-          // (register pressure would cut occupancy to 2 waves per SIMD)
-          if ((z & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+          // Finish every two voxels before the next pair's reads: an empty asm that
+          // takes the accumulator as an operand keeps the compiler from sinking the
+          // math below later reads (it would hoist all eight voxels' reads and hold
+          // their values), so the kernel fits 80 registers and three workgroups per CU
+          if ((z & 1) == 1) {
+            asm volatile("" : "+v"(acc[z]));
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
       }
       if (more) store_stage(buf ^ 1);
