@@ -72,9 +72,9 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (5_122_529_079 + 693_027_568,
-                                 "081f0a7b581fb7c28288707697f0ce7dafb7f11f88c737704aee00254e0977d6"),
-    ("weight_radon", "f32"): (1_045_011_777 + 518_985_461,
+    ("cone_bp_adjoint", "f32"): (3_039_901_521 + 693_063_456,
+                                 "5174c8b6b5b02028f732930dd5b813e223518bf03d14fdef2bc522dfeaf0fabe"),
+    ("weight_radon", "f32"): (1_045_033_562 + 518_984_453,
                               "0dd99e62e381cf9e454098f4e4d14a2f91a4d59c07950c9982e6de8ca2b2f1fd"),
 }
 
