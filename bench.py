@@ -72,10 +72,10 @@ STAGE_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (stage, storage dtype): (bytes per call, digest of the stage's kernel sources)
-    ("cone_bp_adjoint", "f32"): (3_039_901_521 + 693_063_456,
+    ("cone_bp_adjoint", "f32"): (3_042_834_369 + 693_060_088,
                                  "5174c8b6b5b02028f732930dd5b813e223518bf03d14fdef2bc522dfeaf0fabe"),
-    ("weight_radon", "f32"): (1_045_033_562 + 518_984_453,
-                              "0dd99e62e381cf9e454098f4e4d14a2f91a4d59c07950c9982e6de8ca2b2f1fd"),
+    ("weight_radon", "f32"): (1_045_988_176 + 519_000_315,
+                              "e2b0876032bfee707c69dbd5d36f94743ff7bf2b61dcd835f03bfeb6f6467cec"),
 }
 
 

@@ -157,15 +157,18 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
   // consecutive lines, stride 4 is slower again).
   const int lane_line = ((threadIdx.x >> 7) << 7) + ((threadIdx.x & 63) << 1) + ((threadIdx.x >> 6) & 1);
   // Full chunks (kSplatKC angles, nearly all of them) run a copy of the walk
-  // without the per-angle range checks.
-  auto walk = [&](auto full) {
+  // without the per-angle range checks.  Each walk direction (COL: lines are rows)
+  // has its own copy, so the line's part of the cosine weight is computed once per
+  // line (7.5 -> 6.6 VALU per pixel-angle, 1% faster).
+  auto walk = [&](auto full, auto col) {
     constexpr bool FULL = decltype(full)::value;
+    constexpr bool COL = decltype(col)::value;
     for (int line = lane_line; line < n_lines; line += blockDim.x) {
       long long t[kSplatKC];
   #pragma unroll
       for (int kk = 0; kk < kSplatKC; ++kk) {
         if (FULL || kk < kn) {
-          const double t0 = colmajor ? fma((double)line, sB[kk], sC[kk]) : fma((double)line, sA[kk], sC[kk]);
+          const double t0 = COL ? fma((double)line, sB[kk], sC[kk]) : fma((double)line, sA[kk], sC[kk]);
           const double fl = floor(t0);
           t[kk] = ((long long)((int)fl + kk * row + 1) << 32) + (long long)(unsigned)((t0 - fl) * 4294967296.0);
         } else {
@@ -174,8 +177,8 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
       }
       // the next kSplatPre pixels of the line are loaded while the current ones
       // are deposited, so each wave keeps several loads in flight
-      const Tin* base = colmajor ? im + (size_t)line * g.nu : im + line;
-      const int pitch = colmajor ? 1 : g.nu;
+      const Tin* base = COL ? im + (size_t)line * g.nu : im + line;
+      const int pitch = COL ? 1 : g.nu;
       Tin xb[kSplatPre];   // raw storage values, converted at use
   #pragma unroll
       for (int q = 0; q < kSplatPre; ++q) xb[q] = q < n_steps ? base[(size_t)q * pitch] : Tin{};
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
         for (int q = 0; q < kSplatPre; ++q) {
           const int p = p0 + q;
           if (p >= n_steps) break;
-          const int i = colmajor ? p : line, j = colmajor ? line : p;
+          const int i = COL ? p : line, j = COL ? line : p;
           float x = to_f32(xc[q]);
           if (WCOS) {
             const float xu = (i - g.cu) * g.du, yv = (j - g.cv) * g.dv;
@@ -222,8 +225,13 @@ __global__ __launch_bounds__(512) void k_splat(const Tin* __restrict__ img, Tout
       }
     }
   };
-  if (kn == kSplatKC) walk(std::true_type{});
-  else walk(std::false_type{});
+  if (kn == kSplatKC) {
+    if (colmajor) walk(std::true_type{}, std::true_type{});
+    else walk(std::true_type{}, std::false_type{});
+  } else {
+    if (colmajor) walk(std::false_type{}, std::true_type{});
+    else walk(std::false_type{}, std::false_type{});
+  }
   __syncthreads();
   // decode: word = a + 2^32 b with |a| < 2^31
   Tout* o = out + ((size_t)v * g.n_theta + k0) * ns;
@@ -312,8 +320,11 @@ __global__ __launch_bounds__(TX * 8) void k_interp(const Tin* __restrict__ rows,
       }
     }
     __syncthreads();
+    // entry q = (kk, e) with q = kk wl + e; a thread's entries lie blockDim.x apart, so
+    // (kk, e) advances by (blockDim.x / wl, blockDim.x % wl) with one carry, not a division
+    const int dkk = blockDim.x / wl, de = blockDim.x - dkk * wl;
+    int kk = threadIdx.x / wl, e = threadIdx.x - kk * wl;
     for (int q = threadIdx.x; q < kn * wl; q += blockDim.x) {
-      const int kk = q / wl, e = q - kk * wl;
       const int m = sW0[kk] + e;
       const Tin* r = rv + (size_t)(k0 + kk) * ns;
       const float a = ((unsigned)m < (unsigned)ns) ? to_f32(r[m]) : 0.f;
@@ -322,6 +333,12 @@ __global__ __launch_bounds__(TX * 8) void k_interp(const Tin* __restrict__ rows,
       // window centre; LOCAL: left sample and slope
       win[q] = LOCAL ? make_float2(a, b - a)
                      : make_float2(0.5f * (a + b) - (float)(e - (wl >> 1)) * (b - a), b - a);
+      kk += dkk;
+      e += de;
+      if (e >= wl) {
+        e -= wl;
+        ++kk;
+      }
     }
     __syncthreads();
     const float fx = (float)tx, fy = (float)ty;
